@@ -1,0 +1,198 @@
+"""Benchmark of the explicit LDPM step on one MI355X.
+
+Workload: uniaxial tension to fracture of a 100 mm concrete cube (d 4-10 mm,
+seed 1, synthetic specimen from the seeded generator), FP64 path, the whole
+trajectory (warmup + timed steps = 200k explicit steps by default).  Prints
+one JSON line with facet-updates/s, the energy-balance error, the mixed
+(FP32-facet / FP64-state) form's throughput and its peak-stress and energy
+errors against the FP64 path, the facet kernel's HBM roofline fraction
+(HIP-event kernel times) and the FP64 CPU oracle timed on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2603_13190_amd import specimen as S
+    if name == "tension_cube100":
+        s = S.tension_cube(edge=100.0, d0=4.0, da=10.0, seed=1, rate=1e-2, ramp=1e-3)
+        desc = ("uniaxial tension to fracture, 100 mm cube, d 4-10 mm Fuller 0.4, seed 1, "
+                "top-face velocity ramp 1e-3 s to 1e-2 /s, full law")
+        return s, desc, 200000
+    if name == "tension_cube50":
+        s = S.tension_cube(edge=50.0, d0=4.0, da=8.0, seed=1, rate=5e-2, ramp=1e-3)
+        return s, "uniaxial tension, 50 mm cube, d 4-8 mm, seed 1", 20000
+    raise SystemExit(f"unknown workload {name}")
+
+
+def timed_run(sysd, precision, warmup, steps, launch=None):
+    import torch
+    from paper_2603_13190_amd.ldpm import System
+    g = System(sysd, precision=precision)
+    if launch:
+        g.set_launch(**launch)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record()
+    g.step(steps)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = t0.elapsed_time(t1)
+    g.sync()
+    return g, ms, wall
+
+
+def accuracy_run(sysd, precision, total, every, launch=None):
+    """Nominal-stress history (reaction / area) sampled every `every` steps."""
+    from paper_2603_13190_amd.ldpm import System
+    g = System(sysd, precision=precision)
+    if launch:
+        g.set_launch(**launch)
+    prog = sysd["meta"]["load_prog"]
+    area = sysd["meta"]["area"]
+    hist = []
+    done = 0
+    while done < total:
+        k = min(every, total - done)
+        g.step(k)
+        done += k
+        hist.append(g.reaction(prog) / area)
+    en = g.energy()
+    return hist, en, g
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="tension_cube100")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=2000)
+    ap.add_argument("--tets-per-block", type=int, default=16)
+    ap.add_argument("--particle-threads", type=int, default=256)
+    ap.add_argument("--xcd-remap", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the explicit LDPM step is measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    torch.cuda.init()
+    sysd, desc, total = make_workload(args.workload)
+    steps = args.steps if args.steps is not None else total - args.warmup
+    launch = dict(tets_per_block=args.tets_per_block, particle_threads=args.particle_threads,
+                  xcd_remap=args.xcd_remap)
+    N, T, F = sysd["meta"]["N"], sysd["meta"]["T"], sysd["meta"]["F"]
+    log(f"workload {args.workload}: N={N} T={T} F={F} dt={sysd['dt']:.4e} steps={steps} warmup={args.warmup}")
+
+    # ---- FP64, timed ----
+    g64, ms64, wall64 = timed_run(sysd, "fp64", args.warmup, steps, launch)
+    info = g64.info()
+    en64 = g64.energy()
+    v64 = F * steps / (ms64 * 1e-3)
+    log(f"fp64: {ms64:.1f} ms for {steps} steps -> {v64:.4e} facet-upd/s (wall {wall64:.2f} s), "
+        f"energy err {en64['err']:.3e}")
+
+    # ---- roofline of the dominant (facet) kernel, HIP events per launch ----
+    fms, pms = g64.step_profiled(args.profile_steps)
+    favg = fms / args.profile_steps
+    pavg = pms / args.profile_steps
+    achieved = info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9
+    log(f"facet kernel avg {favg * 1e3:.2f} us ({info['facet_kernel_bytes'] / 1e6:.2f} MB alg.) -> "
+        f"{achieved:.0f} GB/s; particle kernel avg {pavg * 1e3:.2f} us")
+    g64.close()
+
+    out = {
+        "metric": "facet-updates/s per explicit step + energy-balance & peak-stress error vs FP64",
+        "value": v64, "unit": "facet-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms64 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "particles": N, "tets": T,
+                   "facets": F, "edge_frames": info["n_edges"], "dt": sysd["dt"],
+                   "trajectory_steps": args.warmup + steps, "launch": launch},
+        "energy_balance_err": en64["err"],
+        "roofline": {"bound": "hbm", "kernel": "k_facet<double,1,%d>" % args.tets_per_block,
+                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "alg_bytes_per_launch": info["facet_kernel_bytes"],
+                     "avg_launch_us": favg * 1e3, "particle_kernel_avg_us": pavg * 1e3},
+    }
+
+    # ---- mixed precision, timed ----
+    if not args.no_mixed:
+        gmx, msmx, _ = timed_run(sysd, "mixed", args.warmup, steps, launch)
+        imx = gmx.info()
+        fms2, _ = gmx.step_profiled(args.profile_steps)
+        favg2 = fms2 / args.profile_steps
+        gmx.close()
+        vmx = F * steps / (msmx * 1e-3)
+        out["mixed"] = {"value": vmx, "ms_per_step": msmx / steps, "speedup_vs_fp64": vmx / v64,
+                        "facet_kernel_avg_us": favg2 * 1e3,
+                        "facet_kernel_GBs": imx["facet_kernel_bytes"] / (favg2 * 1e-3) / 1e9}
+        log(f"mixed: {vmx:.4e} facet-upd/s, speedup {vmx / v64:.2f}x")
+
+    # ---- accuracy: nominal stress histories, FP64 vs mixed ----
+    if not args.no_accuracy:
+        every = max(1, (args.warmup + steps) // 100)
+        h64, e64, g = accuracy_run(sysd, "fp64", args.warmup + steps, every, launch)
+        g.close()
+        peak64 = max(h64)
+        out["peak_stress_fp64_MPa"] = peak64
+        if not args.no_mixed:
+            hmx, emx, g = accuracy_run(sysd, "mixed", args.warmup + steps, every, launch)
+            g.close()
+            peakmx = max(hmx)
+            h64a, hmxa = np.array(h64), np.array(hmx)
+            out["mixed"].update({
+                "peak_stress_err_vs_fp64": abs(peakmx - peak64) / abs(peak64),
+                "stress_history_max_err_vs_fp64": float(np.abs(hmxa - h64a).max() / abs(peak64)),
+                "energy_balance_err": emx["err"],
+                "W_int_rel_err_vs_fp64": abs(emx["W_int"] - e64["W_int"]) / abs(e64["W_int"]),
+            })
+            log(f"peak stress fp64 {peak64:.4f} MPa, mixed {peakmx:.4f} MPa; energy err mixed {emx['err']:.2e}")
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ----
+    if not args.no_cpu:
+        import oracle as O
+        o = O.Oracle(sysd)
+        t = time.perf_counter()
+        o.step(5)
+        per = (time.perf_counter() - t) / 5
+        n = max(10, int(args.cpu_seconds / max(per, 1e-6)))
+        t = time.perf_counter()
+        o.step(n)
+        el = time.perf_counter() - t
+        cores = O.max_threads()
+        out["cpu_baseline"] = {"value": F * n / el, "unit": "facet-updates/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{n} explicit steps (steps 5..{5 + n}) of the same workload, "
+                                         f"{el:.1f} s, OpenMP over facets and particles"}
+        log(f"cpu oracle: {F * n / el:.4e} facet-upd/s on {cores} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

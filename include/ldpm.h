@@ -1,0 +1,225 @@
+/*
+ * ldpm.h - C-ABI of the MI355X explicit LDPM solver library (libldpm.so).
+ *
+ * The library advances the Lattice Discrete Particle Model equations of
+ * motion  M q'' + f_int(q) = f_ext  (paper: "Numerical Implementations",
+ * equation of motion with the lumped, diagonal mass matrix) by the explicit
+ * central-difference scheme used by the paper's explicit solvers.  Each step:
+ *   - facet strains e = P^T [[u]] / l from the translations and rotations of
+ *     the two particles of every facet (eq. strain1),
+ *   - the tetrahedron volumetric strain e_V (appendix, compressive behaviour),
+ *   - the history-dependent facet law t = T(e, s, p) (appendix: fracturing,
+ *     compressive and frictional behaviour; or t = E e),
+ *   - facet forces A P t and moments c x (A P t) gathered onto particles
+ *     (eq. balance) in a fixed order, without floating-point atomics,
+ *   - the leapfrog update of velocities and positions in FP64, with
+ *     prescribed-velocity programs, applied-force programs and reactions,
+ *   - the work of internal and external forces and the kinetic energy
+ *     (numerical-examples section: energy-balance measure).
+ *
+ * Conventions
+ *   - Units are the caller's; the workloads shipped with the project use mm,
+ *     N, MPa, s, tonne.
+ *   - Arrays are structure-of-arrays: "[3][N]" means three consecutive blocks
+ *     of N values (x of all particles, then y, then z).
+ *   - Particle DoF d = 0..5 is (u_x, u_y, u_z, theta_x, theta_y, theta_z).
+ *   - Facets are tetrahedron-major: facet f belongs to tetrahedron f / 12 and
+ *     connects two of its nodes; n_facets == 12 * n_tets.  The order of the
+ *     12 facets inside a tetrahedron is free.
+ *   - Facet k, from particle I to particle J: n_k along I->J, m_k an arbitrary
+ *     unit tangent, l_k = n_k x m_k; c^I_k points from I to the facet
+ *     centroid; c^J_k = c^I_k - len_k n_k (eq. strain1 and eq. balance).
+ *   - Particle I receives +A P t and c^I x (A P t) from its facet k; J
+ *     receives the negatives with c^J (eq. balance).
+ *
+ * Time stepping (central difference, constant dt): the state after n steps
+ * is (q^n, v^{n-1/2}).  Step n evaluates the internal forces at q^n and the
+ * applied forces at t_n = n dt, sets v^{n+1/2} = v^{n-1/2} + h M^{-1} f for
+ * free DoFs (h = dt/2 for the first step from the initial velocity v^0, dt
+ * afterwards), v^{n+1/2} = scale * program(t_{n+1/2}) for prescribed DoFs,
+ * and q^{n+1} = q^n + dt v^{n+1/2}.
+ *
+ * Errors: every call returns an ldpm_status; nothing is thrown across the
+ * ABI and nothing aborts.  ldpm_last_error() returns a thread-local message
+ * for the last failing call.  ldpm_step only enqueues work: a non-finite
+ * velocity raises a sticky device flag that the next synchronising call
+ * (ldpm_read_state, ldpm_energy, ldpm_reaction, ldpm_sync) reports as
+ * LDPM_ERR_UNSTABLE.
+ *
+ * Threading: a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LDPM_H
+#define LDPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldpm_system ldpm_system; /* opaque, owned by the library */
+
+typedef enum {
+    LDPM_OK = 0,
+    LDPM_ERR_ARG = 1,      /* invalid argument or inconsistent system */
+    LDPM_ERR_ALLOC = 2,    /* device or host allocation failed */
+    LDPM_ERR_DEVICE = 3,   /* a HIP call failed */
+    LDPM_ERR_UNSTABLE = 4, /* non-finite state (dt above the stability limit?) */
+    LDPM_ERR_STATE = 5     /* call not valid in the handle's current state */
+} ldpm_status;
+
+/* Facet-law precision. */
+enum {
+    LDPM_PREC_FP64 = 0,  /* everything in FP64 */
+    LDPM_PREC_MIXED = 1  /* facet geometry, history, kinematics and law in FP32;
+                            particle state, gather, integration, energies FP64 */
+};
+
+/* Material parameters, appendix table of parameters (names follow it).
+ * law = 0: elastic t = E0 diag(1, alpha, alpha) e (only E0 and alpha used).
+ * law = 1: fracturing (e_N > 0), compressive (e_N <= 0) and frictional
+ *          behaviour.  r_s must be 0 (the paper leaves the degradation of
+ *          the cohesion with H_s != 0 unspecified): LDPM_ERR_ARG otherwise.
+ * Requires l_t > len_k for every facet (H_t > 0) when law = 1.           */
+typedef struct {
+    double E0, alpha, sigma_t, l_t, r_st, n_t, r_s, k_t;
+    double sigma_c0, Hc0_over_E0, Hc1_over_E0, kc0, kc1, kc2, kc3, Ed_over_E0, beta;
+    double mu0, mu_inf, sigma_N0;
+    int32_t law;
+} ldpm_material;
+
+/* Full dynamic state, used to read the state (ldpm_read_state) and to
+ * resume from it (ldpm_system_desc.init_state).  All pointers are host
+ * memory owned by the caller; a NULL field is skipped on read and means
+ * "zero" (or v0/q0 of the descriptor) on resume.                          */
+typedef struct {
+    double *q;          /* [6][N] displacements and rotations q^n            */
+    double *v;          /* [6][N] v^{n-1/2} (v^0 while step == 0)            */
+    double *t;          /* [3][F] facet traction of the last step (t_N,t_M,t_L) */
+    double *emax;       /* [F]    maximum effective strain reached           */
+    double *fext;       /* [6][N] applied + reaction force of the last step  */
+    double *w_int;      /* [T]    accumulated internal work per tetrahedron  */
+    double *w_ext;      /* [N]    accumulated external work per particle     */
+    double *w_kin;      /* [N]    kinetic energy per particle at the last step */
+    double *w_kin0;     /* [n_specimens] initial kinetic energy              */
+    int64_t step;       /* completed steps n                                 */
+} ldpm_state;
+
+/* System description.  The library copies everything it needs during
+ * ldpm_load_system; the caller may free its arrays afterwards.            */
+typedef struct {
+    int32_t n_specimens;              /* >= 1; independent specimens concatenated */
+    const int64_t *particle_off;      /* [n_specimens+1] or NULL when n_specimens == 1 */
+    const int64_t *tet_off;           /* [n_specimens+1] or NULL when n_specimens == 1 */
+    int64_t n_particles, n_tets, n_facets;  /* N, T, F (F == 12 T) */
+    const double *x0;                 /* [3][N] particle centres */
+    const double *mass;               /* [N]    lumped translational mass (> 0) */
+    const double *rot_inertia;        /* [3][N] lumped rotational inertia (> 0) */
+    const double *cell_vol;           /* [N]    cell volume V_I (used with body_force) */
+    const double *cell_r;             /* [3][N] centre -> cell centroid r_I (with body_force) */
+    const int32_t *tet_nodes;         /* [4][T] node ids; positive orientation not required */
+    const int32_t *facet_I;           /* [F] */
+    const int32_t *facet_J;           /* [F] */
+    const double *facet_cI;           /* [3][F] */
+    const double *facet_n;            /* [3][F] unit, along I->J */
+    const double *facet_m;            /* [3][F] unit, orthogonal to n */
+    const double *facet_area;         /* [F] projected area A_k = A0 n.n0 */
+    const double *facet_len;          /* [F] edge length l_k */
+    const uint8_t *dof_mode;          /* [6][N] 0 free, 1 prescribed velocity */
+    const int32_t *dof_prog;          /* [6][N] program id or -1 (free: applied force
+                                         scale*prog(t); prescribed: velocity) */
+    const double *dof_scale;          /* [6][N] */
+    int32_t n_programs;               /* piecewise-linear programs, constant beyond ends */
+    const int64_t *prog_off;          /* [n_programs+1] */
+    const double *prog_t;             /* [prog_off[n_programs]] increasing times */
+    const double *prog_v;             /* [prog_off[n_programs]] values */
+    const double *body_force;         /* [3] per unit volume, or NULL */
+    const double *q0;                 /* [6][N] or NULL (zero) */
+    const double *v0;                 /* [6][N] or NULL (zero) */
+    const ldpm_state *init_state;     /* resume from a read state, or NULL */
+    const ldpm_material *mat;
+    double dt;                        /* > 0 */
+    int32_t precision;                /* LDPM_PREC_FP64 or LDPM_PREC_MIXED */
+    void *stream;                     /* hipStream_t for all work, or NULL (null stream) */
+    /* Optional device allocator (e.g. a framework's caching allocator);
+     * NULL -> hipMalloc / hipFree.  The library makes one allocation.     */
+    void *(*dev_alloc)(size_t bytes, void *ctx);
+    void (*dev_free)(void *ptr, void *ctx);
+    void *alloc_ctx;
+} ldpm_system_desc;
+
+/* Energies of one specimen after the last completed step n (all at time
+ * t_{n-1}, the last configuration whose internal forces were evaluated).   */
+typedef struct {
+    double W_ext;   /* work of applied forces and reactions */
+    double W_int;   /* work of the facet tractions (trapezoid per facet) */
+    double W_kin;   /* kinetic energy at step n-1, mid-step velocities averaged */
+    double W_kin0;  /* initial kinetic energy */
+    double err;     /* |W_ext + W_kin0 - W_int - W_kin| / max(|W_ext + W_kin0|, tiny) */
+    int64_t step;
+    double time;    /* t_{n-1} */
+} ldpm_energies;
+
+/* Validate the description, build the internal layout (facet-sorted
+ * particle incidence lists, deduplicated edge frames, SoA buffers), allocate
+ * device memory and upload.  On success *out owns everything.             */
+ldpm_status ldpm_load_system(const ldpm_system_desc *desc, ldpm_system **out);
+
+/* Enqueue n_steps explicit steps on the handle's stream (asynchronous). */
+ldpm_status ldpm_step(ldpm_system *s, int64_t n_steps);
+
+/* Like ldpm_step, but brackets every facet-kernel and particle-kernel launch
+ * with HIP events on the handle's stream, waits after each step, and returns
+ * the summed kernel times in milliseconds (for roofline measurements). */
+ldpm_status ldpm_step_profiled(ldpm_system *s, int64_t n_steps, double *facet_ms,
+                               double *particle_ms);
+
+/* Wait for the stream; report a sticky device error. */
+ldpm_status ldpm_sync(ldpm_system *s);
+
+/* Synchronise and copy the state into caller buffers (NULL fields skipped).
+ * out->step receives the number of completed steps.                       */
+ldpm_status ldpm_read_state(ldpm_system *s, ldpm_state *out);
+
+/* Synchronise and reduce the energies of one specimen in a fixed order
+ * (bitwise reproducible, independent of batching).                         */
+ldpm_status ldpm_energy(ldpm_system *s, int32_t specimen, ldpm_energies *out);
+
+/* Synchronise and sum fext over every DoF whose program id is `program`
+ * (the resultant reaction of a loaded face: nominal stress = sum / area). */
+ldpm_status ldpm_reaction(ldpm_system *s, int32_t program, double *out);
+
+/* Counts and layout facts: N, T, F, number of deduplicated edge frames,
+ * algorithmic bytes of one facet step and of one particle step.           */
+typedef struct {
+    int64_t n_particles, n_tets, n_facets, n_edges, n_specimens, step;
+    int32_t precision, law;
+    double facet_kernel_bytes;     /* compulsory HBM bytes per facet-kernel launch */
+    double particle_kernel_bytes;  /* compulsory HBM bytes per particle-kernel launch */
+    size_t device_bytes;           /* device memory held by the handle */
+} ldpm_info;
+ldpm_status ldpm_get_info(ldpm_system *s, ldpm_info *out);
+
+/* Launch configuration of the step: tetrahedra per facet block (16, 32 or
+ * 64), threads per particle block (64..1024, multiple of 64), and whether
+ * the facet kernel's launch order is interleaved across the chip's XCDs.
+ * Results do not depend on it (bitwise).                                   */
+typedef struct {
+    int32_t tets_per_block;
+    int32_t particle_threads;
+    int32_t xcd_remap;
+} ldpm_launch;
+ldpm_status ldpm_set_launch(ldpm_system *s, const ldpm_launch *cfg);
+ldpm_status ldpm_get_launch(ldpm_system *s, ldpm_launch *out);
+
+/* Release device memory and the handle (NULL is a no-op). */
+void ldpm_free(ldpm_system *s);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *ldpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDPM_H */

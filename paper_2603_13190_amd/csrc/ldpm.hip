@@ -1,0 +1,1078 @@
+// MI355X (gfx950) explicit LDPM step behind the C-ABI of include/ldpm.h.
+//
+// Data layout in HBM (structure of arrays):
+//   particles  x0[3][N], q[6][N], v[6][N], mass[N], inertia[3][N],
+//              dof mode/program/scale [6][N], fext[6][N], w_ext[N], w_kin[N],
+//              incidence CSR: ptr[N+1], slot[4T] (slot = 4 tet + local node)
+//   tets       nodes[4][T], w_int[T], contributions [4T][6] (per tet-node)
+//   facets     cI[3][F], area[F], rec[F] (edge-frame id | local I,J code),
+//              history t[3][F], e_max[F]                (FP64 or FP32)
+//   edge frames n[3][E], m[3][E], len[E]  (deduplicated (n, m, len) triples)
+//
+// One step = two kernels:
+//   k_facet    one block per TB tetrahedra, one lane per facet (12 TB lanes).
+//              Node states of the block's tets are staged in LDS; e_V per
+//              tet (eq. for e_V in the appendix); per facet: displacement
+//              jump and strain (eq. strain1), strain increment from the FP64
+//              velocities, constitutive law (appendix), force A P t and
+//              moments c x (A P t) (eq. balance), internal-work increment;
+//              the 6 facets touching each tet node are summed in LDS in a
+//              fixed order, so each tet writes 4 x 6 numbers instead of 12 x 9.
+//   k_particle one lane per particle: gathers its tet-node contributions in
+//              ascending tetrahedron order (CSR, no atomics), adds applied and
+//              body forces, leapfrog update in FP64, reactions, energies.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ldpm.h"
+#include "law.hpp"
+
+using namespace ldpm;
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static ldpm_status fail(ldpm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return fail(LDPM_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device argument blocks
+// ---------------------------------------------------------------------------
+template <typename R>
+struct FacetArgs {
+    const R* __restrict__ cI;      // [3][F]
+    const R* __restrict__ area;    // [F]
+    const int32_t* __restrict__ rec;  // [F]
+    const R* __restrict__ en;      // [3][E]
+    const R* __restrict__ em;      // [3][E]
+    const R* __restrict__ elen;    // [E]
+    R* __restrict__ ht;            // [3][F]
+    R* __restrict__ hemax;         // [F]
+    int64_t F, E;
+};
+
+struct NodeArgs {
+    const int32_t* __restrict__ tet;  // [4][T]
+    const double* __restrict__ x0;    // [3][N]
+    const double* __restrict__ q;     // [6][N]
+    const double* __restrict__ v;     // [6][N]
+    int64_t N, T;
+};
+
+struct ParticleArgs {
+    double* __restrict__ q;           // [6][N]
+    double* __restrict__ v;           // [6][N]
+    const double* __restrict__ mass;  // [N]
+    const double* __restrict__ inertia;  // [3][N]
+    const uint8_t* __restrict__ mode;    // [6][N]
+    const int32_t* __restrict__ prog;    // [6][N]
+    const double* __restrict__ scale;    // [6][N]
+    const double* __restrict__ body;     // [6][N] or nullptr
+    double* __restrict__ fext;           // [6][N]
+    double* __restrict__ wext;           // [N]
+    double* __restrict__ wkin;           // [N]
+    const int32_t* __restrict__ ptr;     // [N+1]
+    const int32_t* __restrict__ slot;    // [4T]
+    const int64_t* __restrict__ prog_off;
+    const double* __restrict__ prog_t;
+    const double* __restrict__ prog_v;
+    int32_t* __restrict__ flag;
+    int64_t N;
+};
+
+// ---------------------------------------------------------------------------
+// facet kernel
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap)
+{
+    // Blocks are dispatched round-robin over the 8 XCDs (each with its own
+    // L2); give every XCD a contiguous range of tet blocks instead, so that
+    // neighbouring tets (which share nodes and edge frames) share an L2.
+    if (!remap) return b;
+    const int64_t x = b & 7, k = b >> 3;
+    const int64_t qn = nb >> 3, r = nb & 7;
+    return x * qn + (x < r ? x : r) + k;
+}
+
+template <typename R, int LAW, int TB>
+__global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
+                                                   R* __restrict__ contrib, double* __restrict__ wint,
+                                                   double dt, int first, int remap)
+{
+    constexpr int NS = 4 * TB;   // node slots per block
+    constexpr int NF = 12 * TB;  // facets per block
+    __shared__ double s_x[3][NS];
+    __shared__ double s_q[6][NS];
+    __shared__ double s_v[6][NS];
+    __shared__ double s_ev[NS];
+    __shared__ R s_F[3][NF];
+    __shared__ R s_MI[3][NF];
+    __shared__ R s_MJ[3][NF];
+    __shared__ double s_w[NF];
+    __shared__ uint8_t s_code[NF];
+
+    const int tid = threadIdx.x;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
+    const int64_t tet0 = blk * TB;
+    const int64_t T = na.T, N = na.N;
+
+    // ---- A: stage the 4 nodes of each tet (slot a*TB + tl) ----
+    if (tid < NS) {
+        const int tl = tid % TB, a = tid / TB;
+        const int64_t tt = tet0 + tl;
+        if (tt < T) {
+            const int64_t nd = na.tet[(int64_t)a * T + tt];
+#pragma unroll
+            for (int c = 0; c < 3; c++) s_x[c][tid] = na.x0[c * N + nd];
+#pragma unroll
+            for (int c = 0; c < 6; c++) s_q[c][tid] = na.q[c * N + nd];
+#pragma unroll
+            for (int c = 0; c < 6; c++) s_v[c][tid] = na.v[c * N + nd];
+        }
+    }
+    __syncthreads();
+
+    // ---- B: e_V contribution grad N_a . u_a of node a of tet tl ----
+    if (tid < NS) {
+        const int tl = tid % TB, a = tid / TB;
+        if (tet0 + tl < T) {
+            int o[3], k = 0;
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+                if (b != a) o[k++] = b * TB + tl;
+            const int sa = tid;
+            // N_a(x) = det[x_b - x, x_c - x, x_d - x] / det[x_b - x_a, x_c - x_a, x_d - x_a]
+            // grad N_a = -((x_c - x_b) x (x_d - x_b)) / det[...]
+            double cb[3], db[3], ba[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                cb[c] = s_x[c][o[1]] - s_x[c][o[0]];
+                db[c] = s_x[c][o[2]] - s_x[c][o[0]];
+                ba[c] = s_x[c][o[0]] - s_x[c][sa];
+            }
+            const double g0 = cb[1] * db[2] - cb[2] * db[1];
+            const double g1 = cb[2] * db[0] - cb[0] * db[2];
+            const double g2 = cb[0] * db[1] - cb[1] * db[0];
+            // det[x_b - x_a, x_c - x_a, x_d - x_a] = (x_b - x_a) . ((x_c - x_b) x (x_d - x_b))
+            const double v6 = ba[0] * g0 + ba[1] * g1 + ba[2] * g2;
+            s_ev[tid] = -(g0 * s_q[0][sa] + g1 * s_q[1][sa] + g2 * s_q[2][sa]) / v6;
+        }
+    }
+    __syncthreads();
+
+    // ---- C: one lane per facet ----
+    if (tid < NF) {
+        const int tl = tid / 12;
+        const int64_t tt = tet0 + tl;
+        double wk = 0.0;
+        uint8_t code = 0xff;
+        if (tt < T) {
+            const int64_t f = tt * 12 + (tid % 12);
+            const int64_t F = fa.F, E = fa.E;
+            const int32_t rc = fa.rec[f];
+            const int aI = (rc >> 28) & 3, aJ = (rc >> 30) & 3;
+            const int64_t r = rc & 0x0fffffff;
+            code = (uint8_t)(aI | (aJ << 2));
+            const int sI = aI * TB + tl, sJ = aJ * TB + tl;
+            const R n0 = fa.en[r], n1 = fa.en[E + r], n2 = fa.en[2 * E + r];
+            const R m0 = fa.em[r], m1 = fa.em[E + r], m2 = fa.em[2 * E + r];
+            const R len = fa.elen[r];
+            const R l0 = n1 * m2 - n2 * m1, l1 = n2 * m0 - n0 * m2, l2 = n0 * m1 - n1 * m0;
+            const R cI0 = fa.cI[f], cI1 = fa.cI[F + f], cI2 = fa.cI[2 * F + f];
+            const R cJ0 = cI0 - len * n0, cJ1 = cI1 - len * n1, cJ2 = cI2 - len * n2;
+            const R A = fa.area[f];
+            R tv[3] = {fa.ht[f], fa.ht[F + f], fa.ht[2 * F + f]};
+            R emx = LAW != 0 ? fa.hemax[f] : R(0);
+            const R told0 = tv[0], told1 = tv[1], told2 = tv[2];
+            // displacement jump [[u]] = u_J + th_J x c^J - u_I - th_I x c^I
+            // (translation difference in FP64, rotation terms in R)
+            R d[3], dv[3];
+            {
+                const R du0 = (R)(s_q[0][sJ] - s_q[0][sI]);
+                const R du1 = (R)(s_q[1][sJ] - s_q[1][sI]);
+                const R du2 = (R)(s_q[2][sJ] - s_q[2][sI]);
+                const R tI0 = (R)s_q[3][sI], tI1 = (R)s_q[4][sI], tI2 = (R)s_q[5][sI];
+                const R tJ0 = (R)s_q[3][sJ], tJ1 = (R)s_q[4][sJ], tJ2 = (R)s_q[5][sJ];
+                d[0] = du0 + (tJ1 * cJ2 - tJ2 * cJ1) - (tI1 * cI2 - tI2 * cI1);
+                d[1] = du1 + (tJ2 * cJ0 - tJ0 * cJ2) - (tI2 * cI0 - tI0 * cI2);
+                d[2] = du2 + (tJ0 * cJ1 - tJ1 * cJ0) - (tI0 * cI1 - tI1 * cI0);
+                const R dv0 = (R)(s_v[0][sJ] - s_v[0][sI]);
+                const R dv1 = (R)(s_v[1][sJ] - s_v[1][sI]);
+                const R dv2 = (R)(s_v[2][sJ] - s_v[2][sI]);
+                const R wI0 = (R)s_v[3][sI], wI1 = (R)s_v[4][sI], wI2 = (R)s_v[5][sI];
+                const R wJ0 = (R)s_v[3][sJ], wJ1 = (R)s_v[4][sJ], wJ2 = (R)s_v[5][sJ];
+                dv[0] = dv0 + (wJ1 * cJ2 - wJ2 * cJ1) - (wI1 * cI2 - wI2 * cI1);
+                dv[1] = dv1 + (wJ2 * cJ0 - wJ0 * cJ2) - (wI2 * cI0 - wI0 * cI2);
+                dv[2] = dv2 + (wJ0 * cJ1 - wJ1 * cJ0) - (wI0 * cI1 - wI1 * cI0);
+            }
+            const R il = R(1) / len;
+            R e[3], de[3];
+            e[0] = (n0 * d[0] + n1 * d[1] + n2 * d[2]) * il;
+            e[1] = (m0 * d[0] + m1 * d[1] + m2 * d[2]) * il;
+            e[2] = (l0 * d[0] + l1 * d[1] + l2 * d[2]) * il;
+            if (first) {  // history starts from the undeformed state
+                de[0] = e[0];
+                de[1] = e[1];
+                de[2] = e[2];
+            } else {      // q^n - q^{n-1} = dt v^{n-1/2}
+                const R s = (R)dt * il;
+                de[0] = (n0 * dv[0] + n1 * dv[1] + n2 * dv[2]) * s;
+                de[1] = (m0 * dv[0] + m1 * dv[1] + m2 * dv[2]) * s;
+                de[2] = (l0 * dv[0] + l1 * dv[1] + l2 * dv[2]) * s;
+            }
+            const R eV = (R)((s_ev[tl] + s_ev[TB + tl] + s_ev[2 * TB + tl] + s_ev[3 * TB + tl]) / 3.0);
+            facet_law<R, LAW>(mat, len, e, de, eV, tv, emx);
+            fa.ht[f] = tv[0];
+            fa.ht[F + f] = tv[1];
+            fa.ht[2 * F + f] = tv[2];
+            if (LAW != 0) fa.hemax[f] = emx;
+            // internal work A l (t_old + t)/2 . de
+            wk = (double)(A * len * R(0.5) *
+                          ((told0 + tv[0]) * de[0] + (told1 + tv[1]) * de[1] + (told2 + tv[2]) * de[2]));
+            // facet force A P t and its moments about I and J
+            const R F0 = A * (tv[0] * n0 + tv[1] * m0 + tv[2] * l0);
+            const R F1 = A * (tv[0] * n1 + tv[1] * m1 + tv[2] * l1);
+            const R F2 = A * (tv[0] * n2 + tv[1] * m2 + tv[2] * l2);
+            s_F[0][tid] = F0;
+            s_F[1][tid] = F1;
+            s_F[2][tid] = F2;
+            s_MI[0][tid] = cI1 * F2 - cI2 * F1;
+            s_MI[1][tid] = cI2 * F0 - cI0 * F2;
+            s_MI[2][tid] = cI0 * F1 - cI1 * F0;
+            s_MJ[0][tid] = cJ1 * F2 - cJ2 * F1;
+            s_MJ[1][tid] = cJ2 * F0 - cJ0 * F2;
+            s_MJ[2][tid] = cJ0 * F1 - cJ1 * F0;
+        }
+        s_w[tid] = wk;
+        s_code[tid] = code;
+    }
+    __syncthreads();
+
+    // ---- D: per tet node, sum its 6 facets in ascending local order ----
+    if (tid < NS) {
+        const int tl = tid >> 2, a = tid & 3;
+        const int64_t tt = tet0 + tl;
+        if (tt < T) {
+            R acc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int j = 0; j < 12; j++) {
+                const int fl = tl * 12 + j;
+                const int cd = s_code[fl];
+                if ((cd & 3) == a) {
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        acc[c] += s_F[c][fl];
+                        acc[3 + c] += s_MI[c][fl];
+                    }
+                } else if (((cd >> 2) & 3) == a) {
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        acc[c] -= s_F[c][fl];
+                        acc[3 + c] -= s_MJ[c][fl];
+                    }
+                }
+            }
+            R* out = contrib + (tt * 4 + a) * 6;
+#pragma unroll
+            for (int c = 0; c < 6; c++) out[c] = acc[c];
+            if (a == 0) {
+                double w = 0.0;
+#pragma unroll
+                for (int j = 0; j < 12; j++) w += s_w[tl * 12 + j];
+                wint[tt] += w;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// particle kernel
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double prog_eval(const ParticleArgs& pa, int32_t p, double time)
+{
+    if (p < 0) return 0.0;
+    const int64_t a = pa.prog_off[p], b = pa.prog_off[p + 1];
+    if (b <= a) return 0.0;
+    if (time <= pa.prog_t[a]) return pa.prog_v[a];
+    for (int64_t i = a; i + 1 < b; i++) {
+        const double t1 = pa.prog_t[i + 1];
+        if (time <= t1) {
+            const double t0 = pa.prog_t[i];
+            const double w = (time - t0) / (t1 - t0);
+            return pa.prog_v[i] + w * (pa.prog_v[i + 1] - pa.prog_v[i]);
+        }
+    }
+    return pa.prog_v[b - 1];
+}
+
+template <typename R>
+__global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __restrict__ contrib,
+                                                   int64_t n, double dt)
+{
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = pa.N;
+    if (I >= N) return;
+    double f[6] = {0, 0, 0, 0, 0, 0};
+    const int32_t s0 = pa.ptr[I], s1 = pa.ptr[I + 1];
+    for (int32_t s = s0; s < s1; s++) {
+        const R* c = contrib + (int64_t)pa.slot[s] * 6;
+#pragma unroll
+        for (int d = 0; d < 6; d++) f[d] += (double)c[d];
+    }
+    const double time = (double)n * dt;
+    const double h = (n == 0) ? 0.5 * dt : dt;
+    const double t_half = ((double)n + 0.5) * dt;
+    double wk = 0.0, dwe = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        const int64_t id = d * N + I;
+        const double M = d < 3 ? pa.mass[I] : pa.inertia[(d - 3) * N + I];
+        double applied = pa.body ? pa.body[id] : 0.0;
+        const int32_t pg = pa.prog[id];
+        const uint8_t md = pa.mode[id];
+        if (md == 0 && pg >= 0) applied += pa.scale[id] * prog_eval(pa, pg, time);
+        const double fnet = f[d] + applied;
+        const double vold = pa.v[id];
+        double vnew, Fd;
+        if (md == 0) {
+            vnew = vold + h * fnet / M;
+            Fd = applied;
+        } else {
+            vnew = (pg >= 0) ? pa.scale[id] * prog_eval(pa, pg, t_half) : 0.0;
+            const double R_ = M * (vnew - vold) / h - fnet;  // reaction
+            Fd = applied + R_;
+        }
+        if (n > 0) dwe += 0.5 * (pa.fext[id] + Fd) * (dt * vold);
+        const double vb = (n == 0) ? vold : 0.5 * (vold + vnew);
+        wk += 0.5 * M * vb * vb;
+        pa.fext[id] = Fd;
+        pa.v[id] = vnew;
+        pa.q[id] += dt * vnew;
+        bad |= !isfinite(vnew);
+    }
+    pa.wext[I] += dwe;
+    pa.wkin[I] = wk;
+    if (bad) pa.flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions (fixed strided order + fixed LDS tree)
+// ---------------------------------------------------------------------------
+constexpr int RED_THREADS = 256;
+
+__device__ double block_sum_fixed(double x)
+{
+    __shared__ double s[RED_THREADS];
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = s[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_energy(const double* __restrict__ wint, int64_t t0,
+                                                        int64_t t1, const double* __restrict__ wext,
+                                                        const double* __restrict__ wkin, int64_t p0,
+                                                        int64_t p1, double* __restrict__ out)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += RED_THREADS) a += wint[i];
+    for (int64_t i = p0 + threadIdx.x; i < p1; i += RED_THREADS) {
+        b += wext[i];
+        c += wkin[i];
+    }
+    a = block_sum_fixed(a);
+    b = block_sum_fixed(b);
+    c = block_sum_fixed(c);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+        out[2] = c;
+    }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reaction(const double* __restrict__ fext,
+                                                          const int32_t* __restrict__ prog, int64_t n6,
+                                                          int32_t p, double* __restrict__ out)
+{
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n6; i += RED_THREADS)
+        if (prog[i] == p) a += fext[i];
+    a = block_sum_fixed(a);
+    if (threadIdx.x == 0) out[0] = a;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct ldpm_system {
+    int64_t N = 0, T = 0, F = 0, E = 0;
+    int32_t nspec = 1, prec = 0, law = 1;
+    std::vector<int64_t> poff, toff;
+    std::vector<double> wkin0;
+    double dt = 0;
+    int64_t step = 0;
+    hipStream_t stream = nullptr;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    void (*dev_free)(void*, void*) = nullptr;
+    void* alloc_ctx = nullptr;
+    int device = 0;
+    ldpm_launch launch{16, 256, 1};
+    // device pointers
+    double *x0, *q, *v, *mass, *inertia, *scale, *body, *fext, *wext, *wkin, *wint;
+    uint8_t* mode;
+    int32_t *prog, *ptr, *slot, *tet, *rec, *flag;
+    int64_t* prog_off;
+    double *prog_t, *prog_v, *red;
+    void *cI, *area, *en, *em, *elen, *ht, *hemax, *contrib;
+    int64_t n_prog_pts = 0, n_prog = 0;
+    MatDev<double> matd;
+    MatDev<float> matf;
+};
+
+namespace {
+
+struct Carve {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        const size_t o = off;
+        off += count * sizeof(T);
+        return o;
+    }
+};
+
+template <typename R>
+MatDev<R> make_mat(const ldpm_material& m)
+{
+    MatDev<R> p;
+    const double E0 = m.E0, al = m.alpha;
+    p.E0 = (R)E0;
+    p.alpha = (R)al;
+    p.aE0 = (R)(al * E0);
+    p.inv_alpha = (R)(1.0 / al);
+    p.sigma_t = (R)m.sigma_t;
+    p.l_t = (R)m.l_t;
+    p.c4 = (R)(4.0 * al / (m.r_st * m.r_st));
+    p.n_t = (R)m.n_t;
+    p.Hs_over_alpha = (R)(m.r_s * E0 / al);
+    p.k_t = (R)m.k_t;
+    p.sigma_c0 = (R)m.sigma_c0;
+    p.Hc0 = (R)(m.Hc0_over_E0 * E0);
+    p.Hc1 = (R)(m.Hc1_over_E0 * E0);
+    p.kc1 = (R)m.kc1;
+    p.kc2 = (R)m.kc2;
+    p.eV0 = (R)(m.kc3 * m.sigma_c0 / E0);
+    const double ec0 = m.sigma_c0 / E0;
+    p.ec0 = (R)ec0;
+    p.ec1 = (R)(m.kc0 * ec0);
+    p.Ed = (R)(m.Ed_over_E0 * E0);
+    p.beta = (R)m.beta;
+    const double ss = m.r_st * m.sigma_t;
+    p.sigma_s = (R)ss;
+    p.sigma_s2 = (R)(ss * ss);
+    p.dmu_sN0 = (R)((m.mu0 - m.mu_inf) * m.sigma_N0);
+    p.mu_inf = (R)m.mu_inf;
+    p.inv_sigma_N0 = (R)(1.0 / m.sigma_N0);
+    p.two_over_pi = (R)(2.0 / M_PI);
+    return p;
+}
+
+bool finite_all(const double* p, int64_t n)
+{
+    for (int64_t i = 0; i < n; i++)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+struct FrameKey {
+    double v[7];
+    bool operator==(const FrameKey& o) const { return memcmp(v, o.v, sizeof(v)) == 0; }
+};
+struct FrameHash {
+    size_t operator()(const FrameKey& k) const
+    {
+        uint64_t h = 1469598103934665603ull;
+        const unsigned char* p = (const unsigned char*)k.v;
+        for (size_t i = 0; i < sizeof(k.v); i++) h = (h ^ p[i]) * 1099511628211ull;
+        return (size_t)h;
+    }
+};
+
+template <typename R>
+void to_r(std::vector<unsigned char>& buf, const double* src, size_t n)
+{
+    buf.resize(n * sizeof(R));
+    R* d = (R*)buf.data();
+    for (size_t i = 0; i < n; i++) d[i] = (R)src[i];
+}
+
+size_t rbytes(int prec) { return prec == LDPM_PREC_MIXED ? 4 : 8; }
+
+}  // namespace
+
+template <typename R, int LAW, int TB>
+static void launch_facet_t(ldpm_system* s, int first)
+{
+    NodeArgs na{s->tet, s->x0, s->q, s->v, s->N, s->T};
+    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->en, (const R*)s->em,
+                    (const R*)s->elen, (R*)s->ht, (R*)s->hemax, s->F, s->E};
+    const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
+    const int64_t nb = (s->T + TB - 1) / TB;
+    hipLaunchKernelGGL((k_facet<R, LAW, TB>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
+                       (R*)s->contrib, s->wint, s->dt, first, s->launch.xcd_remap);
+}
+
+template <typename R, int LAW>
+static void launch_facet_l(ldpm_system* s, int first)
+{
+    switch (s->launch.tets_per_block) {
+    case 32: launch_facet_t<R, LAW, 32>(s, first); break;
+    case 64: launch_facet_t<R, LAW, 64>(s, first); break;
+    default: launch_facet_t<R, LAW, 16>(s, first); break;
+    }
+}
+
+static void launch_facet(ldpm_system* s, int first)
+{
+    if (s->prec == LDPM_PREC_MIXED) {
+        if (s->law == 0) launch_facet_l<float, 0>(s, first);
+        else launch_facet_l<float, 1>(s, first);
+    } else {
+        if (s->law == 0) launch_facet_l<double, 0>(s, first);
+        else launch_facet_l<double, 1>(s, first);
+    }
+}
+
+static void launch_particle(ldpm_system* s, int64_t n)
+{
+    ParticleArgs pa{s->q,     s->v,    s->mass, s->inertia, s->mode,     s->prog,   s->scale,
+                    s->body,  s->fext, s->wext, s->wkin,    s->ptr,      s->slot,   s->prog_off,
+                    s->prog_t, s->prog_v, s->flag, s->N};
+    const int th = s->launch.particle_threads;
+    const unsigned nb = (unsigned)((s->N + th - 1) / th);
+    if (s->prec == LDPM_PREC_MIXED)
+        hipLaunchKernelGGL(k_particle<float>, dim3(nb), dim3(th), 0, s->stream, pa, (const float*)s->contrib, n,
+                           s->dt);
+    else
+        hipLaunchKernelGGL(k_particle<double>, dim3(nb), dim3(th), 0, s->stream, pa, (const double*)s->contrib, n,
+                           s->dt);
+}
+
+extern "C" {
+
+const char* ldpm_last_error(void) { return g_err.c_str(); }
+
+ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
+{
+    g_err.clear();
+    if (!d || !out) return fail(LDPM_ERR_ARG, "null descriptor or output");
+    *out = nullptr;
+    const int64_t N = d->n_particles, T = d->n_tets, F = d->n_facets;
+    if (N <= 0 || T <= 0) return fail(LDPM_ERR_ARG, "empty system (N=%lld, T=%lld)", (long long)N, (long long)T);
+    if (F != 12 * T) return fail(LDPM_ERR_ARG, "n_facets (%lld) must be 12 * n_tets (%lld)", (long long)F, (long long)T);
+    if (N >= (1ll << 31) || 4 * T >= (1ll << 31) || F >= (1ll << 40))
+        return fail(LDPM_ERR_ARG, "system too large for 32-bit incidence indices");
+    if (!d->x0 || !d->mass || !d->rot_inertia || !d->tet_nodes || !d->facet_I || !d->facet_J || !d->facet_cI ||
+        !d->facet_n || !d->facet_m || !d->facet_area || !d->facet_len || !d->dof_mode || !d->dof_prog ||
+        !d->dof_scale || !d->mat)
+        return fail(LDPM_ERR_ARG, "missing required array");
+    if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(LDPM_ERR_ARG, "dt must be positive and finite");
+    if (d->precision != LDPM_PREC_FP64 && d->precision != LDPM_PREC_MIXED)
+        return fail(LDPM_ERR_ARG, "unknown precision %d", d->precision);
+    const ldpm_material& mat = *d->mat;
+    if (mat.law != 0 && mat.law != 1) return fail(LDPM_ERR_ARG, "law must be 0 or 1");
+    if (!(mat.E0 > 0) || !(mat.alpha > 0)) return fail(LDPM_ERR_ARG, "E0 and alpha must be positive");
+    if (mat.law == 1) {
+        if (mat.r_s != 0.0) return fail(LDPM_ERR_ARG, "r_s != 0 (shear softening of the cohesion) is not supported");
+        if (!(mat.sigma_t > 0) || !(mat.r_st > 0) || !(mat.sigma_c0 > 0) || !(mat.sigma_N0 > 0) || !(mat.kc3 > 0))
+            return fail(LDPM_ERR_ARG, "sigma_t, r_st, sigma_c0, sigma_N0 and kc3 must be positive");
+    }
+    const int nspec = d->n_specimens <= 0 ? 1 : d->n_specimens;
+    std::vector<int64_t> poff(nspec + 1), toff(nspec + 1);
+    if (nspec == 1 && (!d->particle_off || !d->tet_off)) {
+        poff = {0, N};
+        toff = {0, T};
+    } else {
+        if (!d->particle_off || !d->tet_off) return fail(LDPM_ERR_ARG, "batched system needs particle_off and tet_off");
+        for (int i = 0; i <= nspec; i++) {
+            poff[i] = d->particle_off[i];
+            toff[i] = d->tet_off[i];
+        }
+        if (poff[0] != 0 || toff[0] != 0 || poff[nspec] != N || toff[nspec] != T)
+            return fail(LDPM_ERR_ARG, "specimen offsets must start at 0 and end at N, T");
+        for (int i = 0; i < nspec; i++)
+            if (poff[i + 1] <= poff[i] || toff[i + 1] <= toff[i])
+                return fail(LDPM_ERR_ARG, "specimen %d is empty", i);
+    }
+    // ---- validation of values and indices ----
+    if (!finite_all(d->x0, 3 * N) || !finite_all(d->facet_cI, 3 * F) || !finite_all(d->facet_n, 3 * F) ||
+        !finite_all(d->facet_m, 3 * F) || !finite_all(d->facet_area, F) || !finite_all(d->facet_len, F) ||
+        !finite_all(d->dof_scale, 6 * N))
+        return fail(LDPM_ERR_ARG, "non-finite geometry or loading input");
+    for (int64_t i = 0; i < N; i++) {
+        if (!(d->mass[i] > 0)) return fail(LDPM_ERR_ARG, "mass[%lld] must be positive", (long long)i);
+        for (int c = 0; c < 3; c++)
+            if (!(d->rot_inertia[c * N + i] > 0))
+                return fail(LDPM_ERR_ARG, "rot_inertia of particle %lld must be positive", (long long)i);
+    }
+    // specimen of each particle (tets and facets must stay inside one specimen)
+    std::vector<int32_t> spec_of(N);
+    for (int s = 0; s < nspec; s++)
+        for (int64_t i = poff[s]; i < poff[s + 1]; i++) spec_of[i] = s;
+    for (int s = 0; s < nspec; s++)
+        for (int64_t t = toff[s]; t < toff[s + 1]; t++)
+            for (int a = 0; a < 4; a++) {
+                const int64_t nd = d->tet_nodes[a * T + t];
+                if (nd < 0 || nd >= N) return fail(LDPM_ERR_ARG, "tet %lld: node index out of range", (long long)t);
+                if (spec_of[nd] != s) return fail(LDPM_ERR_ARG, "tet %lld crosses specimens", (long long)t);
+            }
+    const int64_t nP = d->n_programs;
+    if (nP < 0 || (nP > 0 && (!d->prog_off || !d->prog_t || !d->prog_v)))
+        return fail(LDPM_ERR_ARG, "programs: missing arrays");
+    int64_t npts = 0;
+    if (nP > 0) {
+        if (d->prog_off[0] != 0) return fail(LDPM_ERR_ARG, "prog_off[0] must be 0");
+        for (int64_t p = 0; p < nP; p++) {
+            if (d->prog_off[p + 1] < d->prog_off[p]) return fail(LDPM_ERR_ARG, "prog_off must be non-decreasing");
+            for (int64_t i = d->prog_off[p]; i + 1 < d->prog_off[p + 1]; i++)
+                if (!(d->prog_t[i + 1] > d->prog_t[i])) return fail(LDPM_ERR_ARG, "program %lld: times must increase", (long long)p);
+        }
+        npts = d->prog_off[nP];
+        if (!finite_all(d->prog_t, npts) || !finite_all(d->prog_v, npts)) return fail(LDPM_ERR_ARG, "non-finite program");
+    }
+    for (int64_t i = 0; i < 6 * N; i++) {
+        if (d->dof_mode[i] > 1) return fail(LDPM_ERR_ARG, "dof_mode must be 0 or 1");
+        if (d->dof_prog[i] < -1 || d->dof_prog[i] >= nP) return fail(LDPM_ERR_ARG, "dof_prog out of range");
+    }
+    // ---- facets: local codes and deduplicated edge frames ----
+    std::vector<int32_t> rec(F);
+    std::vector<double> en, em, el;
+    std::unordered_map<FrameKey, int32_t, FrameHash> frames;
+    frames.reserve((size_t)(F / 4 + 16));
+    for (int64_t f = 0; f < F; f++) {
+        const int64_t t = f / 12;
+        const int32_t I = d->facet_I[f], J = d->facet_J[f];
+        int aI = -1, aJ = -1;
+        for (int a = 0; a < 4; a++) {
+            if (d->tet_nodes[a * T + t] == I) aI = a;
+            if (d->tet_nodes[a * T + t] == J) aJ = a;
+        }
+        if (aI < 0 || aJ < 0 || aI == aJ)
+            return fail(LDPM_ERR_ARG, "facet %lld: I and J must be two distinct nodes of tet %lld", (long long)f, (long long)t);
+        const double len = d->facet_len[f];
+        if (!(len > 0)) return fail(LDPM_ERR_ARG, "facet %lld: non-positive length", (long long)f);
+        if (mat.law == 1 && !(mat.l_t > len))
+            return fail(LDPM_ERR_ARG, "facet %lld: l_t must exceed the edge length (H_t > 0)", (long long)f);
+        FrameKey k;
+        for (int c = 0; c < 3; c++) {
+            k.v[c] = d->facet_n[c * F + f];
+            k.v[3 + c] = d->facet_m[c * F + f];
+        }
+        k.v[6] = len;
+        auto it = frames.find(k);
+        int32_t r;
+        if (it == frames.end()) {
+            r = (int32_t)el.size();
+            if (r >= (1 << 28)) return fail(LDPM_ERR_ARG, "too many distinct facet frames");
+            frames.emplace(k, r);
+            for (int c = 0; c < 3; c++) {
+                en.push_back(k.v[c]);
+                em.push_back(k.v[3 + c]);
+            }
+            el.push_back(len);
+        } else {
+            r = it->second;
+        }
+        rec[f] = (int32_t)((uint32_t)r | ((uint32_t)aI << 28) | ((uint32_t)aJ << 30));
+    }
+    const int64_t E = (int64_t)el.size();
+    // SoA frames [3][E]
+    std::vector<double> enS(3 * E), emS(3 * E);
+    for (int64_t r = 0; r < E; r++)
+        for (int c = 0; c < 3; c++) {
+            enS[c * E + r] = en[3 * r + c];
+            emS[c * E + r] = em[3 * r + c];
+        }
+    // ---- incidence CSR: slots 4t+a in ascending order ----
+    std::vector<int32_t> ptr(N + 1, 0), slot(4 * T);
+    for (int64_t t = 0; t < T; t++)
+        for (int a = 0; a < 4; a++) ptr[d->tet_nodes[a * T + t] + 1]++;
+    for (int64_t i = 0; i < N; i++) ptr[i + 1] += ptr[i];
+    {
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t t = 0; t < T; t++)
+            for (int a = 0; a < 4; a++) slot[fill[d->tet_nodes[a * T + t]]++] = (int32_t)(4 * t + a);
+    }
+    // ---- body force: constant generalised force V_I b, V_I r_I x b ----
+    std::vector<double> body;
+    if (d->body_force && (d->body_force[0] != 0 || d->body_force[1] != 0 || d->body_force[2] != 0)) {
+        if (!d->cell_vol || !d->cell_r) return fail(LDPM_ERR_ARG, "body_force needs cell_vol and cell_r");
+        const double* b = d->body_force;
+        body.resize(6 * N);
+        for (int64_t i = 0; i < N; i++) {
+            const double V = d->cell_vol[i];
+            const double r0 = d->cell_r[i], r1 = d->cell_r[N + i], r2 = d->cell_r[2 * N + i];
+            body[0 * N + i] = V * b[0];
+            body[1 * N + i] = V * b[1];
+            body[2 * N + i] = V * b[2];
+            body[3 * N + i] = V * (r1 * b[2] - r2 * b[1]);
+            body[4 * N + i] = V * (r2 * b[0] - r0 * b[2]);
+            body[5 * N + i] = V * (r0 * b[1] - r1 * b[0]);
+        }
+    }
+    // ---- layout ----
+    const int prec = d->precision;
+    const size_t rb = rbytes(prec);
+    Carve cv;
+    const size_t o_x0 = cv.take<double>(3 * N), o_q = cv.take<double>(6 * N), o_v = cv.take<double>(6 * N);
+    const size_t o_mass = cv.take<double>(N), o_in = cv.take<double>(3 * N), o_scale = cv.take<double>(6 * N);
+    const size_t o_body = body.empty() ? 0 : cv.take<double>(6 * N);
+    const size_t o_fext = cv.take<double>(6 * N), o_wext = cv.take<double>(N), o_wkin = cv.take<double>(N);
+    const size_t o_wint = cv.take<double>(T), o_mode = cv.take<uint8_t>(6 * N), o_prog = cv.take<int32_t>(6 * N);
+    const size_t o_ptr = cv.take<int32_t>(N + 1), o_slot = cv.take<int32_t>(4 * T), o_tet = cv.take<int32_t>(4 * T);
+    const size_t o_rec = cv.take<int32_t>(F), o_flag = cv.take<int32_t>(4);
+    const size_t o_poff = cv.take<int64_t>(nP + 1), o_pt = cv.take<double>(npts + 1), o_pv = cv.take<double>(npts + 1);
+    const size_t o_red = cv.take<double>(8);
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_cI = cv.off; cv.off += 3 * F * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_area = cv.off; cv.off += F * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_en = cv.off; cv.off += 3 * E * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_em = cv.off; cv.off += 3 * E * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_el = cv.off; cv.off += E * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_ht = cv.off; cv.off += 3 * F * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_hem = cv.off; cv.off += F * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t o_con = cv.off; cv.off += 4 * T * 6 * rb;
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t total = cv.off;
+
+    ldpm_system* s = new ldpm_system();
+    s->N = N; s->T = T; s->F = F; s->E = E; s->nspec = nspec; s->prec = prec; s->law = mat.law;
+    s->poff = poff; s->toff = toff; s->dt = d->dt;
+    s->stream = (hipStream_t)d->stream;
+    s->dev_free = d->dev_alloc ? d->dev_free : nullptr;
+    s->alloc_ctx = d->alloc_ctx;
+    s->n_prog = nP; s->n_prog_pts = npts;
+    s->matd = make_mat<double>(mat);
+    s->matf = make_mat<float>(mat);
+    (void)hipGetDevice(&s->device);
+    void* base = nullptr;
+    if (d->dev_alloc) {
+        base = d->dev_alloc(total, d->alloc_ctx);
+        if (!base) { delete s; return fail(LDPM_ERR_ALLOC, "device allocator returned NULL for %zu bytes", total); }
+    } else {
+        if (hipMalloc(&base, total) != hipSuccess) { delete s; return fail(LDPM_ERR_ALLOC, "hipMalloc(%zu) failed", total); }
+    }
+    s->arena = base;
+    s->arena_bytes = total;
+    char* B = (char*)base;
+    s->x0 = (double*)(B + o_x0); s->q = (double*)(B + o_q); s->v = (double*)(B + o_v);
+    s->mass = (double*)(B + o_mass); s->inertia = (double*)(B + o_in); s->scale = (double*)(B + o_scale);
+    s->body = body.empty() ? nullptr : (double*)(B + o_body);
+    s->fext = (double*)(B + o_fext); s->wext = (double*)(B + o_wext); s->wkin = (double*)(B + o_wkin);
+    s->wint = (double*)(B + o_wint); s->mode = (uint8_t*)(B + o_mode); s->prog = (int32_t*)(B + o_prog);
+    s->ptr = (int32_t*)(B + o_ptr); s->slot = (int32_t*)(B + o_slot); s->tet = (int32_t*)(B + o_tet);
+    s->rec = (int32_t*)(B + o_rec); s->flag = (int32_t*)(B + o_flag);
+    s->prog_off = (int64_t*)(B + o_poff); s->prog_t = (double*)(B + o_pt); s->prog_v = (double*)(B + o_pv);
+    s->red = (double*)(B + o_red);
+    s->cI = B + o_cI; s->area = B + o_area; s->en = B + o_en; s->em = B + o_em; s->elen = B + o_el;
+    s->ht = B + o_ht; s->hemax = B + o_hem; s->contrib = B + o_con;
+
+    auto H2D = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->stream);
+    };
+    std::vector<std::vector<unsigned char>> keep;  // host staging kept alive until sync
+    auto put_r = [&](void* dst, const double* src, size_t n) -> hipError_t {
+        keep.emplace_back();
+        if (prec == LDPM_PREC_MIXED) to_r<float>(keep.back(), src, n);
+        else to_r<double>(keep.back(), src, n);
+        return H2D(dst, keep.back().data(), n * rb);
+    };
+    hipError_t e = hipSuccess;
+    const ldpm_state* is = d->init_state;
+    std::vector<double> zeros6(6 * N, 0.0);
+    const double* q0 = (is && is->q) ? is->q : (d->q0 ? d->q0 : zeros6.data());
+    const double* v0 = (is && is->v) ? is->v : (d->v0 ? d->v0 : zeros6.data());
+    if (!finite_all(q0, 6 * N) || !finite_all(v0, 6 * N)) {
+        ldpm_free(s);
+        return fail(LDPM_ERR_ARG, "non-finite initial state");
+    }
+#define CK(x) do { e = (x); if (e != hipSuccess) { ldpm_free(s); return fail(LDPM_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e)); } } while (0)
+    CK(H2D(s->x0, d->x0, 3 * N * 8));
+    CK(H2D(s->q, q0, 6 * N * 8));
+    CK(H2D(s->v, v0, 6 * N * 8));
+    CK(H2D(s->mass, d->mass, N * 8));
+    CK(H2D(s->inertia, d->rot_inertia, 3 * N * 8));
+    CK(H2D(s->scale, d->dof_scale, 6 * N * 8));
+    if (s->body) CK(H2D(s->body, body.data(), 6 * N * 8));
+    CK(H2D(s->mode, d->dof_mode, 6 * N));
+    CK(H2D(s->prog, d->dof_prog, 6 * N * 4));
+    CK(H2D(s->ptr, ptr.data(), (N + 1) * 4));
+    CK(H2D(s->slot, slot.data(), 4 * T * 4));
+    CK(H2D(s->tet, d->tet_nodes, 4 * T * 4));
+    CK(H2D(s->rec, rec.data(), F * 4));
+    std::vector<int64_t> po(nP + 1, 0);
+    for (int64_t p = 0; p <= nP && nP > 0; p++) po[p] = d->prog_off[p];
+    CK(H2D(s->prog_off, po.data(), (nP + 1) * 8));
+    if (npts > 0) {
+        CK(H2D(s->prog_t, d->prog_t, npts * 8));
+        CK(H2D(s->prog_v, d->prog_v, npts * 8));
+    }
+    CK(put_r(s->cI, d->facet_cI, 3 * F));
+    CK(put_r(s->area, d->facet_area, F));
+    CK(put_r(s->en, enS.data(), 3 * E));
+    CK(put_r(s->em, emS.data(), 3 * E));
+    CK(put_r(s->elen, el.data(), E));
+    // history, accumulators
+    std::vector<double> zF(3 * F, 0.0);
+    CK(put_r(s->ht, (is && is->t) ? is->t : zF.data(), 3 * F));
+    CK(put_r(s->hemax, (is && is->emax) ? is->emax : zF.data(), F));
+    CK(H2D(s->fext, (is && is->fext) ? is->fext : zeros6.data(), 6 * N * 8));
+    CK(H2D(s->wext, (is && is->w_ext) ? is->w_ext : zeros6.data(), N * 8));
+    CK(H2D(s->wkin, (is && is->w_kin) ? is->w_kin : zeros6.data(), N * 8));
+    std::vector<double> zT(T, 0.0);
+    CK(H2D(s->wint, (is && is->w_int) ? is->w_int : zT.data(), T * 8));
+    CK(hipMemsetAsync(s->flag, 0, 16, s->stream));
+    CK(hipMemsetAsync(s->contrib, 0, 4 * T * 6 * rb, s->stream));
+#undef CK
+    // initial kinetic energy per specimen, particle order then DoF order
+    s->wkin0.assign(nspec, 0.0);
+    if (is && is->w_kin0) {
+        for (int i = 0; i < nspec; i++) s->wkin0[i] = is->w_kin0[i];
+    } else {
+        for (int sp = 0; sp < nspec; sp++) {
+            double w = 0.0;
+            for (int64_t i = poff[sp]; i < poff[sp + 1]; i++)
+                for (int dd = 0; dd < 6; dd++) {
+                    const double M = dd < 3 ? d->mass[i] : d->rot_inertia[(dd - 3) * N + i];
+                    const double vv = v0[dd * N + i];
+                    w += 0.5 * M * vv * vv;
+                }
+            s->wkin0[sp] = w;
+        }
+    }
+    s->step = is ? is->step : 0;
+    if (s->step < 0) { ldpm_free(s); return fail(LDPM_ERR_ARG, "negative step in init_state"); }
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) { ldpm_free(s); return fail(LDPM_ERR_DEVICE, "upload sync failed: %s", hipGetErrorString(e)); }
+    *out = s;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_step(ldpm_system* s, int64_t n_steps)
+{
+    if (!s) return fail(LDPM_ERR_ARG, "null handle");
+    if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
+    for (int64_t i = 0; i < n_steps; i++) {
+        launch_facet(s, s->step == 0 ? 1 : 0);
+        launch_particle(s, s->step);
+        s->step++;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_step_profiled(ldpm_system* s, int64_t n_steps, double* facet_ms, double* particle_ms)
+{
+    if (!s || !facet_ms || !particle_ms) return fail(LDPM_ERR_ARG, "null argument");
+    if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
+    hipEvent_t ev[3];
+    for (int i = 0; i < 3; i++) HIP_TRY(hipEventCreate(&ev[i]));
+    double fsum = 0.0, psum = 0.0;
+    hipError_t e = hipSuccess;
+    for (int64_t i = 0; i < n_steps && e == hipSuccess; i++) {
+        e = hipEventRecord(ev[0], s->stream);
+        launch_facet(s, s->step == 0 ? 1 : 0);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
+        launch_particle(s, s->step);
+        s->step++;
+        if (e == hipSuccess) e = hipEventRecord(ev[2], s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+        float a = 0.f, b = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[1], ev[2]);
+        fsum += a;
+        psum += b;
+    }
+    for (int i = 0; i < 3; i++) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "profiled step failed: %s", hipGetErrorString(e));
+    *facet_ms = fsum;
+    *particle_ms = psum;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_sync(ldpm_system* s)
+{
+    if (!s) return fail(LDPM_ERR_ARG, "null handle");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    int32_t flag = 0;
+    HIP_TRY(hipMemcpy(&flag, s->flag, 4, hipMemcpyDeviceToHost));
+    if (flag) return fail(LDPM_ERR_UNSTABLE, "non-finite velocity: the step is unstable");
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_read_state(ldpm_system* s, ldpm_state* o)
+{
+    if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
+    ldpm_status st = ldpm_sync(s);
+    if (st != LDPM_OK && st != LDPM_ERR_UNSTABLE) return st;
+    const int64_t N = s->N, T = s->T, F = s->F;
+    if (o->q) HIP_TRY(hipMemcpy(o->q, s->q, 6 * N * 8, hipMemcpyDeviceToHost));
+    if (o->v) HIP_TRY(hipMemcpy(o->v, s->v, 6 * N * 8, hipMemcpyDeviceToHost));
+    if (o->fext) HIP_TRY(hipMemcpy(o->fext, s->fext, 6 * N * 8, hipMemcpyDeviceToHost));
+    if (o->w_int) HIP_TRY(hipMemcpy(o->w_int, s->wint, T * 8, hipMemcpyDeviceToHost));
+    if (o->w_ext) HIP_TRY(hipMemcpy(o->w_ext, s->wext, N * 8, hipMemcpyDeviceToHost));
+    if (o->w_kin) HIP_TRY(hipMemcpy(o->w_kin, s->wkin, N * 8, hipMemcpyDeviceToHost));
+    if (o->w_kin0) for (int i = 0; i < s->nspec; i++) o->w_kin0[i] = s->wkin0[i];
+    auto get_r = [&](double* dst, const void* src, size_t n) -> hipError_t {
+        if (s->prec == LDPM_PREC_MIXED) {
+            std::vector<float> tmp(n);
+            hipError_t e = hipMemcpy(tmp.data(), src, n * 4, hipMemcpyDeviceToHost);
+            for (size_t i = 0; i < n; i++) dst[i] = tmp[i];
+            return e;
+        }
+        return hipMemcpy(dst, src, n * 8, hipMemcpyDeviceToHost);
+    };
+    if (o->t) HIP_TRY(get_r(o->t, s->ht, 3 * F));
+    if (o->emax) HIP_TRY(get_r(o->emax, s->hemax, F));
+    o->step = s->step;
+    return st;
+}
+
+ldpm_status ldpm_energy(ldpm_system* s, int32_t sp, ldpm_energies* o)
+{
+    if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
+    if (sp < 0 || sp >= s->nspec) return fail(LDPM_ERR_ARG, "specimen %d out of range", sp);
+    hipLaunchKernelGGL(k_energy, dim3(1), dim3(RED_THREADS), 0, s->stream, s->wint, s->toff[sp], s->toff[sp + 1],
+                       s->wext, s->wkin, s->poff[sp], s->poff[sp + 1], s->red);
+    HIP_TRY(hipGetLastError());
+    ldpm_status st = ldpm_sync(s);
+    if (st != LDPM_OK && st != LDPM_ERR_UNSTABLE) return st;
+    double r[3];
+    HIP_TRY(hipMemcpy(r, s->red, 24, hipMemcpyDeviceToHost));
+    o->W_int = r[0];
+    o->W_ext = r[1];
+    o->W_kin = s->step > 0 ? r[2] : s->wkin0[sp];
+    o->W_kin0 = s->wkin0[sp];
+    const double den = std::max(std::fabs(o->W_ext + o->W_kin0), 1e-300);
+    o->err = std::fabs(o->W_ext + o->W_kin0 - o->W_int - o->W_kin) / den;
+    o->step = s->step;
+    o->time = (double)(s->step > 0 ? s->step - 1 : 0) * s->dt;
+    return st;
+}
+
+ldpm_status ldpm_reaction(ldpm_system* s, int32_t program, double* out)
+{
+    if (!s || !out) return fail(LDPM_ERR_ARG, "null argument");
+    hipLaunchKernelGGL(k_reaction, dim3(1), dim3(RED_THREADS), 0, s->stream, s->fext, s->prog, 6 * s->N, program,
+                       s->red + 4);
+    HIP_TRY(hipGetLastError());
+    ldpm_status st = ldpm_sync(s);
+    if (st != LDPM_OK && st != LDPM_ERR_UNSTABLE) return st;
+    HIP_TRY(hipMemcpy(out, s->red + 4, 8, hipMemcpyDeviceToHost));
+    return st;
+}
+
+ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
+{
+    if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
+    const double rb = (double)rbytes(s->prec);
+    o->n_particles = s->N;
+    o->n_tets = s->T;
+    o->n_facets = s->F;
+    o->n_edges = s->E;
+    o->n_specimens = s->nspec;
+    o->step = s->step;
+    o->precision = s->prec;
+    o->law = s->law;
+    const double N = (double)s->N, T = (double)s->T, F = (double)s->F, E = (double)s->E;
+    // facet kernel: each array touched once per launch
+    //   facets: rec 4 + cI 3R + area R + history (t 3R + e_max R) read and written
+    //   edge frames 7R per frame; tets: nodes 16 B, w_int 16 B (r+w), contributions 24R
+    //   particles: x0, q, v (15 doubles)
+    const double hist = (s->law == 1 ? 4.0 : 3.0) * rb;
+    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + hist + 3.0 * rb) + E * 7.0 * rb + T * (16.0 + 16.0 + 24.0 * rb) +
+                            N * 15.0 * 8.0;
+    // particle kernel: contributions 24R per tet, slot ids, ptr, particle state
+    //   q, v, fext (r+w 6 doubles each), mass + inertia 4 doubles, scale 6, prog 6x4,
+    //   mode 6, w_ext r+w, w_kin w
+    o->particle_kernel_bytes = T * (24.0 * rb + 16.0) + N * (4.0 + 6 * 8 * 2 * 3 + 4 * 8 + 6 * 8 + 24 + 6 + 16 + 8);
+    o->device_bytes = s->arena_bytes;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_set_launch(ldpm_system* s, const ldpm_launch* c)
+{
+    if (!s || !c) return fail(LDPM_ERR_ARG, "null argument");
+    if (c->tets_per_block != 16 && c->tets_per_block != 32 && c->tets_per_block != 64)
+        return fail(LDPM_ERR_ARG, "tets_per_block must be 16, 32 or 64");
+    if (c->particle_threads < 64 || c->particle_threads > 1024 || c->particle_threads % 64)
+        return fail(LDPM_ERR_ARG, "particle_threads must be a multiple of 64 in [64, 1024]");
+    s->launch = *c;
+    s->launch.xcd_remap = c->xcd_remap ? 1 : 0;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_get_launch(ldpm_system* s, ldpm_launch* o)
+{
+    if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
+    *o = s->launch;
+    return LDPM_OK;
+}
+
+void ldpm_free(ldpm_system* s)
+{
+    if (!s) return;
+    if (s->arena) {
+        (void)hipStreamSynchronize(s->stream);
+        if (s->dev_free) s->dev_free(s->arena, s->alloc_ctx);
+        else (void)hipFree(s->arena);
+    }
+    delete s;
+}
+
+}  // extern "C"

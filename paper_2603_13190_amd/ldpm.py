@@ -1,0 +1,359 @@
+"""Thin Python binding of libldpm.so (the C-ABI declared in include/ldpm.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  PyTorch provides device memory (through its caching allocator) and
+the stream.  There is no fallback: if the library is missing or no GPU is
+visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldpm.so")
+
+LDPM_OK, LDPM_ERR_ARG, LDPM_ERR_ALLOC, LDPM_ERR_DEVICE, LDPM_ERR_UNSTABLE, LDPM_ERR_STATE = range(6)
+PREC = {"fp64": 0, "mixed": 1}
+_STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_DEVICE", 4: "ERR_UNSTABLE", 5: "ERR_STATE"}
+
+EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "ldpm_read_state", "ldpm_energy",
+           "ldpm_reaction", "ldpm_get_info", "ldpm_set_launch", "ldpm_get_launch", "ldpm_free",
+           "ldpm_last_error")
+
+_MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
+               "sigma_c0", "Hc0_over_E0", "Hc1_over_E0", "kc0", "kc1", "kc2", "kc3",
+               "Ed_over_E0", "beta", "mu0", "mu_inf", "sigma_N0")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+_up = C.POINTER(C.c_uint8)
+
+
+class Material(C.Structure):
+    _fields_ = [(k, C.c_double) for k in _MAT_FIELDS] + [("law", C.c_int32)]
+
+
+class State(C.Structure):
+    _fields_ = [("q", _dp), ("v", _dp), ("t", _dp), ("emax", _dp), ("fext", _dp),
+                ("w_int", _dp), ("w_ext", _dp), ("w_kin", _dp), ("w_kin0", _dp),
+                ("step", C.c_int64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [("n_specimens", C.c_int32), ("particle_off", _lp), ("tet_off", _lp),
+                ("n_particles", C.c_int64), ("n_tets", C.c_int64), ("n_facets", C.c_int64),
+                ("x0", _dp), ("mass", _dp), ("rot_inertia", _dp), ("cell_vol", _dp), ("cell_r", _dp),
+                ("tet_nodes", _ip), ("facet_I", _ip), ("facet_J", _ip),
+                ("facet_cI", _dp), ("facet_n", _dp), ("facet_m", _dp),
+                ("facet_area", _dp), ("facet_len", _dp),
+                ("dof_mode", _up), ("dof_prog", _ip), ("dof_scale", _dp),
+                ("n_programs", C.c_int32), ("prog_off", _lp), ("prog_t", _dp), ("prog_v", _dp),
+                ("body_force", _dp), ("q0", _dp), ("v0", _dp), ("init_state", C.POINTER(State)),
+                ("mat", C.POINTER(Material)), ("dt", C.c_double), ("precision", C.c_int32),
+                ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class Energies(C.Structure):
+    _fields_ = [("W_ext", C.c_double), ("W_int", C.c_double), ("W_kin", C.c_double),
+                ("W_kin0", C.c_double), ("err", C.c_double), ("step", C.c_int64),
+                ("time", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("n_tets", C.c_int64), ("n_facets", C.c_int64),
+                ("n_edges", C.c_int64), ("n_specimens", C.c_int64), ("step", C.c_int64),
+                ("precision", C.c_int32), ("law", C.c_int32),
+                ("facet_kernel_bytes", C.c_double), ("particle_kernel_bytes", C.c_double),
+                ("device_bytes", C.c_size_t)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("tets_per_block", C.c_int32), ("particle_threads", C.c_int32),
+                ("xcd_remap", C.c_int32)]
+
+
+class LdpmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ldpm {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libldpm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2603_13190_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.ldpm_load_system.argtypes = [C.POINTER(SystemDesc), C.POINTER(C.c_void_p)]
+        L.ldpm_step.argtypes = [C.c_void_p, C.c_int64]
+        L.ldpm_sync.argtypes = [C.c_void_p]
+        L.ldpm_step_profiled.argtypes = [C.c_void_p, C.c_int64, _dp, _dp]
+        L.ldpm_read_state.argtypes = [C.c_void_p, C.POINTER(State)]
+        L.ldpm_energy.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Energies)]
+        L.ldpm_reaction.argtypes = [C.c_void_p, C.c_int32, _dp]
+        L.ldpm_get_info.argtypes = [C.c_void_p, C.POINTER(Info)]
+        L.ldpm_set_launch.argtypes = [C.c_void_p, C.POINTER(Launch)]
+        L.ldpm_get_launch.argtypes = [C.c_void_p, C.POINTER(Launch)]
+        L.ldpm_free.argtypes = [C.c_void_p]
+        L.ldpm_free.restype = None
+        L.ldpm_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("ldpm_free", "ldpm_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != LDPM_OK:
+        raise LdpmError(rc, lib().ldpm_last_error().decode())
+    return rc
+
+
+def _soa(a, dtype=np.float64):
+    """(n, k) generator layout -> [k][n] contiguous."""
+    a = np.asarray(a)
+    if a.ndim == 1:
+        return np.ascontiguousarray(a, dtype=dtype)
+    return np.ascontiguousarray(a.T, dtype=dtype)
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator on its current stream."""
+
+    def __init__(self, torch, device):
+        self.torch = torch
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device, self.stream)
+            except Exception:  # noqa: BLE001 - allocator failure is reported as NULL
+                return None
+            self.live[ptr] = nbytes
+            return ptr
+
+        def _free(ptr, ctx):
+            if ptr in self.live:
+                del self.live[ptr]
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self.c_alloc = ALLOC_FN(_alloc)
+        self.c_free = FREE_FN(_free)
+
+
+def make_desc(sysd, precision="fp64"):
+    """SystemDesc for a generator dict (host arrays only, no device work).
+    Returns (desc, keepalive) - the arrays must outlive the load call."""
+    N = int(sysd["x0"].shape[0])
+    T = int(sysd["tet_nodes"].shape[0])
+    F = int(sysd["facet_I"].shape[0])
+    k = {}
+    k["x0"] = _soa(sysd["x0"])
+    k["mass"] = _soa(sysd["mass"])
+    k["inertia"] = _soa(sysd["inertia"])
+    k["cell_vol"] = _soa(sysd["cell_vol"])
+    k["cell_r"] = _soa(sysd["cell_r"])
+    k["tet"] = _soa(sysd["tet_nodes"], np.int32)
+    k["fI"] = _soa(sysd["facet_I"], np.int32)
+    k["fJ"] = _soa(sysd["facet_J"], np.int32)
+    k["cI"] = _soa(sysd["facet_cI"])
+    k["n"] = _soa(sysd["facet_n"])
+    k["m"] = _soa(sysd["facet_m"])
+    k["A"] = _soa(sysd["facet_area"])
+    k["len"] = _soa(sysd["facet_len"])
+    k["mode"] = _soa(sysd["dof_mode"], np.uint8)
+    k["prog"] = _soa(sysd["dof_prog"], np.int32)
+    k["scale"] = _soa(sysd["dof_scale"])
+    k["poff"] = np.ascontiguousarray(sysd["prog_off"], dtype=np.int64)
+    k["pt"] = np.ascontiguousarray(sysd["prog_t"], dtype=np.float64)
+    k["pv"] = np.ascontiguousarray(sysd["prog_v"], dtype=np.float64)
+    k["body"] = np.ascontiguousarray(sysd.get("body_force", np.zeros(3)), dtype=np.float64)
+    k["q0"] = _soa(sysd["q0"])
+    k["v0"] = _soa(sysd["v0"])
+    nspec = 1
+    if "particle_off" in sysd:
+        k["po"] = np.ascontiguousarray(sysd["particle_off"], dtype=np.int64)
+        k["to"] = np.ascontiguousarray(sysd["tet_off"], dtype=np.int64)
+        nspec = int(k["po"].size - 1)
+    mat = Material(**{f: float(sysd["material"][f]) for f in _MAT_FIELDS},
+                   law=int(sysd["material"].get("law", 1)))
+    k["mat"] = mat
+    d = SystemDesc()
+    d.n_specimens = nspec
+    if "po" in k:
+        d.particle_off = _p(k["po"], _lp)
+        d.tet_off = _p(k["to"], _lp)
+    d.n_particles, d.n_tets, d.n_facets = N, T, F
+    d.x0 = _p(k["x0"], _dp)
+    d.mass = _p(k["mass"], _dp)
+    d.rot_inertia = _p(k["inertia"], _dp)
+    d.cell_vol = _p(k["cell_vol"], _dp)
+    d.cell_r = _p(k["cell_r"], _dp)
+    d.tet_nodes = _p(k["tet"], _ip)
+    d.facet_I = _p(k["fI"], _ip)
+    d.facet_J = _p(k["fJ"], _ip)
+    d.facet_cI = _p(k["cI"], _dp)
+    d.facet_n = _p(k["n"], _dp)
+    d.facet_m = _p(k["m"], _dp)
+    d.facet_area = _p(k["A"], _dp)
+    d.facet_len = _p(k["len"], _dp)
+    d.dof_mode = _p(k["mode"], _up)
+    d.dof_prog = _p(k["prog"], _ip)
+    d.dof_scale = _p(k["scale"], _dp)
+    d.n_programs = int(k["poff"].size - 1)
+    d.prog_off = _p(k["poff"], _lp)
+    d.prog_t = _p(k["pt"], _dp)
+    d.prog_v = _p(k["pv"], _dp)
+    d.body_force = _p(k["body"], _dp)
+    d.q0 = _p(k["q0"], _dp)
+    d.v0 = _p(k["v0"], _dp)
+    d.mat = C.pointer(mat)
+    d.dt = float(sysd["dt"])
+    d.precision = PREC[precision]
+    return d, k
+
+
+def try_load(desc):
+    """Call ldpm_load_system; returns (status, message, handle or None)."""
+    h = C.c_void_p()
+    rc = lib().ldpm_load_system(C.byref(desc), C.byref(h))
+    return rc, lib().ldpm_last_error().decode(), (h if rc == LDPM_OK else None)
+
+
+class System:
+    """One loaded LDPM system on the GPU.
+
+    sysd: dict from paper_2603_13190_amd.specimen (particle-major arrays),
+    precision: "fp64" or "mixed", init_state: dict from read_state() to
+    resume, torch_alloc: take device memory from torch's caching allocator.
+    """
+
+    def __init__(self, sysd, precision="fp64", init_state: Optional[dict] = None,
+                 torch_alloc=True, device=0):
+        import torch  # device memory and stream provider
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the LDPM library needs a HIP device")
+        torch.cuda.set_device(device)
+        self.N = int(sysd["x0"].shape[0])
+        self.T = int(sysd["tet_nodes"].shape[0])
+        self.F = int(sysd["facet_I"].shape[0])
+        self.nspec = int(len(sysd.get("particle_off", [0, self.N])) - 1)
+        self.dt = float(sysd["dt"])
+        self.precision = precision
+        d, keep = make_desc(sysd, precision)
+        if init_state is not None:
+            self._init_arrays, st = self._state_struct(init_state, fill=True)
+            d.init_state = C.pointer(st)
+            keep["init"] = st
+        self.stream = torch.cuda.current_stream(device)
+        d.stream = C.c_void_p(self.stream.cuda_stream)
+        self._alloc = None
+        if torch_alloc:
+            self._alloc = _TorchAllocator(torch, device)
+            d.dev_alloc = self._alloc.c_alloc
+            d.dev_free = self._alloc.c_free
+        h = C.c_void_p()
+        _check(lib().ldpm_load_system(C.byref(d), C.byref(h)))
+        self.h = h
+        self._keep = (keep, d)
+
+    # ------------------------------------------------------------------
+    def _state_struct(self, state=None, fill=False):
+        N, T, F = self.N, self.T, self.F
+        shapes = dict(q=(6, N), v=(6, N), t=(3, F), emax=(F,), fext=(6, N), w_int=(T,),
+                      w_ext=(N,), w_kin=(N,), w_kin0=(self.nspec,))
+        arrs = {}
+        st = State()
+        for name, shp in shapes.items():
+            if fill:
+                if state is None or state.get(name) is None:
+                    continue
+                src = np.asarray(state[name], dtype=np.float64)
+                a = np.ascontiguousarray(src.T if src.ndim == 2 else src)
+                assert a.shape == shp, (name, a.shape, shp)
+            else:
+                a = np.zeros(shp)
+            arrs[name] = a
+            setattr(st, name, _p(a, _dp))
+        st.step = int(state.get("step", 0)) if (fill and state is not None) else 0
+        return arrs, st
+
+    def step(self, n=1):
+        _check(lib().ldpm_step(self.h, int(n)))
+        return self
+
+    def step_profiled(self, n):
+        """n steps with per-kernel HIP-event timing; returns (facet_ms, particle_ms) sums."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib().ldpm_step_profiled(self.h, int(n), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def sync(self):
+        _check(lib().ldpm_sync(self.h))
+
+    def read_state(self):
+        """State in the generator's particle-major layout (q (N,6), t (F,3), ...)."""
+        arrs, st = self._state_struct()
+        _check(lib().ldpm_read_state(self.h, C.byref(st)))
+        out = {k: (v.T.copy() if v.ndim == 2 else v.copy()) for k, v in arrs.items()}
+        out["step"] = int(st.step)
+        return out
+
+    def energy(self, specimen=0):
+        e = Energies()
+        _check(lib().ldpm_energy(self.h, int(specimen), C.byref(e)))
+        return dict(W_ext=e.W_ext, W_int=e.W_int, W_kin=e.W_kin, W_kin0=e.W_kin0, err=e.err,
+                    step=int(e.step), time=e.time)
+
+    def reaction(self, program):
+        out = C.c_double()
+        _check(lib().ldpm_reaction(self.h, int(program), C.byref(out)))
+        return float(out.value)
+
+    def info(self):
+        i = Info()
+        _check(lib().ldpm_get_info(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def set_launch(self, tets_per_block=16, particle_threads=256, xcd_remap=1):
+        c = Launch(tets_per_block, particle_threads, xcd_remap)
+        _check(lib().ldpm_set_launch(self.h, C.byref(c)))
+
+    def get_launch(self):
+        c = Launch()
+        _check(lib().ldpm_get_launch(self.h, C.byref(c)))
+        return dict(tets_per_block=c.tets_per_block, particle_threads=c.particle_threads,
+                    xcd_remap=c.xcd_remap)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ldpm_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

@@ -1,0 +1,253 @@
+"""GPU (HIP library, through the C-ABI) against the FP64 CPU oracle.
+
+FP64 path: one-step maps from identical states agree to 1e-12 relative per
+field, trajectories to 1e-9 relative (the bar stated for the FP64 path);
+integer/bitwise properties (determinism, batching, launch shapes, resume) are
+exact.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2603_13190_amd import specimen as S
+from tests.gpu_util import (confined_small, elastic_small, oracle_state, rel, tension_full,
+                            tension_small)
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-12
+TOL_TRAJ = 1e-9
+
+
+def gpu(sysd, **kw):
+    from paper_2603_13190_amd.ldpm import System
+    return System(sysd, **kw)
+
+
+def compare(g, o, fields=("q", "v", "t", "emax", "fext"), tol=TOL_TRAJ, what=""):
+    st = g.read_state()
+    errs = {}
+    for f in fields:
+        ref = getattr(o, f)
+        errs[f] = rel(st[f], ref)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{what}: relative errors above {tol}: {errs}"
+    return errs
+
+
+def test_library_is_the_hip_extension():
+    from paper_2603_13190_amd import ldpm
+    L = ldpm.lib()
+    assert L._name.endswith("libldpm.so")
+
+
+@pytest.mark.parametrize("tb", [16, 32, 64])
+def test_one_step_maps_elastic(tb):
+    s = elastic_small()
+    o = O.Oracle(s).step(37)
+    g = gpu(s, init_state=oracle_state(o))
+    g.set_launch(tets_per_block=tb)
+    o.step(1)
+    g.step(1)
+    compare(g, o, tol=TOL_STEP, what=f"elastic TB={tb}")
+
+
+def test_first_step_from_rest_and_initial_velocity():
+    s = elastic_small()
+    o = O.Oracle(s).step(1)
+    g = gpu(s).step(1)
+    compare(g, o, tol=TOL_STEP, what="first step")
+
+
+@pytest.mark.parametrize("n_before", [50, 400, 900])
+def test_one_step_maps_tension(n_before):
+    """One step from oracle states before the peak, around it and after it."""
+    s = tension_small()
+    o = O.Oracle(s).step(n_before)
+    g = gpu(s, init_state=oracle_state(o))
+    o.step(1)
+    g.step(1)
+    compare(g, o, tol=TOL_STEP, what=f"tension after {n_before}")
+
+
+@pytest.mark.parametrize("n_before", [300, 900, 1400])
+def test_one_step_maps_confined_compression(n_before):
+    s = confined_small()
+    o = O.Oracle(s).step(n_before)
+    assert (o.t[:, 0] < 0).any()
+    g = gpu(s, init_state=oracle_state(o))
+    o.step(1)
+    g.step(1)
+    compare(g, o, tol=TOL_STEP, what=f"confined after {n_before}")
+
+
+def test_trajectory_elastic_vibration():
+    s = elastic_small()
+    o = O.Oracle(s)
+    g = gpu(s)
+    for chunk in (1, 99, 400, 1500):
+        o.step(chunk)
+        g.step(chunk)
+        compare(g, o, fields=("q", "v", "t", "fext"), what=f"elastic step {o.step_index}")
+    eo, eg = o.energies(), g.energy()
+    for k in ("W_int", "W_ext", "W_kin", "W_kin0"):
+        assert abs(eg[k] - eo[k]) <= TOL_TRAJ * max(abs(eo[k]), eo["W_kin0"]), (k, eg[k], eo[k])
+
+
+def test_trajectory_tension_prepeak():
+    s = tension_small()
+    o = O.Oracle(s)
+    g = gpu(s)
+    for chunk in (10, 90, 200):
+        o.step(chunk)
+        g.step(chunk)
+        compare(g, o, what=f"tension step {o.step_index}")
+    eo, eg = o.energies(), g.energy()
+    for k in ("W_int", "W_ext", "W_kin"):
+        assert abs(eg[k] - eo[k]) <= TOL_TRAJ * abs(eo[k]), (k, eg[k], eo[k])
+
+
+def test_trajectory_tension_postpeak_reported():
+    """Past the peak the response is history- and branch-sensitive: compare
+    the nominal stress history and energies (divergence is reported)."""
+    s = tension_small()
+    o = O.Oracle(s)
+    g = gpu(s)
+    prog = s["meta"]["load_prog"]
+    so, sg = [], []
+    for _ in range(12):
+        o.step(100)
+        g.step(100)
+        so.append(o.reaction_sum(prog))
+        sg.append(g.reaction(prog))
+    so, sg = np.array(so), np.array(sg)
+    assert np.abs(o.emax).max() > 10 * 4.0 / 43700.0      # well past the peak strain
+    assert abs(sg.max() - so.max()) <= 1e-6 * abs(so).max()
+    st = g.read_state()
+    print("post-peak relative q difference", rel(st["q"], o.q))
+    assert rel(st["q"], o.q) < 1e-6
+
+
+def test_full_size_tension_sampled():
+    """The full 100 mm workload at the benchmark's launch shape: a few
+    hundred steps against the oracle, all fields."""
+    s = tension_full()
+    o = O.Oracle(s).step(150)
+    g = gpu(s)
+    g.set_launch(tets_per_block=16, particle_threads=256, xcd_remap=1)
+    g.step(150)
+    compare(g, o, what="full-size tension")
+
+
+def test_determinism_bitwise():
+    s = tension_small()
+    a = gpu(s).step(700).read_state()
+    b = gpu(s).step(700).read_state()
+    for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_launch_shape_does_not_change_results():
+    s = tension_small()
+    ref = None
+    for tb, pt, rm in ((16, 256, 1), (32, 128, 0), (64, 512, 1), (16, 64, 0)):
+        g = gpu(s)
+        g.set_launch(tets_per_block=tb, particle_threads=pt, xcd_remap=rm)
+        st = g.step(300).read_state()
+        if ref is None:
+            ref = st
+        else:
+            for k in ("q", "v", "t", "emax", "w_int"):
+                assert np.array_equal(st[k], ref[k]), (tb, pt, rm, k)
+
+
+def test_resume_is_bitwise():
+    s = tension_small()
+    full = gpu(s).step(500).read_state()
+    g1 = gpu(s).step(230)
+    mid = g1.read_state()
+    g2 = gpu(s, init_state=mid).step(270)
+    st = g2.read_state()
+    for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
+        assert np.array_equal(st[k], full[k]), k
+    assert st["step"] == 500
+
+
+def test_batched_equals_alone_bitwise():
+    specs = [S.tension_cube(edge=e, d0=4.0, da=8.0, seed=i, rate=2.0, ramp=2e-4)
+             for i, e in enumerate((20.0, 26.0, 23.0))]
+    dt = min(x["dt"] for x in specs)
+    batch = S.concat_specimens(specs, dt=dt)
+    gb = gpu(batch).step(300)
+    sb = gb.read_state()
+    po, to = batch["particle_off"], batch["tet_off"]
+    for i, sp in enumerate(specs):
+        sp = dict(sp)
+        sp["dt"] = dt
+        st = gpu(sp).step(300).read_state()
+        assert np.array_equal(sb["q"][po[i]:po[i + 1]], st["q"])
+        assert np.array_equal(sb["t"][12 * to[i]:12 * to[i + 1]], st["t"])
+        eb = gb.energy(i)
+        ea = gpu(sp).step(300).energy()
+        for k in ("W_int", "W_ext", "W_kin", "W_kin0"):
+            assert eb[k] == ea[k], (i, k)
+
+
+def test_single_tet_and_ragged_blocks():
+    """One tetrahedron (a block with 15 empty tet slots) and a system whose
+    tet count is not a multiple of any block size."""
+    for s in (S.single_tet(), S.few_particle(17, seed=9)):
+        s = dict(s)
+        rng = np.random.default_rng(0)
+        s["v0"] = rng.normal(size=s["v0"].shape) * 1e-1
+        o = O.Oracle(s).step(60)
+        for tb in (16, 64):
+            g = gpu(s)
+            g.set_launch(tets_per_block=tb)
+            g.step(60)
+            compare(g, o, fields=("q", "v", "t", "emax"), what=f"{s['name']} TB={tb}")
+
+
+def test_body_force():
+    s = dict(S.few_particle(12, seed=3))
+    s["body_force"] = np.array([1e-4, -2e-4, 3e-4])
+    o = O.Oracle(s).step(80)
+    g = gpu(s).step(80)
+    compare(g, o, fields=("q", "v", "fext"), what="body force")
+
+
+def test_unstable_step_is_reported():
+    """dt far above the stability limit: non-finite velocities raise the
+    sticky flag and the next synchronising call reports it."""
+    from paper_2603_13190_amd.ldpm import LDPM_ERR_UNSTABLE, LdpmError
+    s = dict(S.few_particle(12, seed=3))
+    s["dt"] = s["dt"] * 50
+    s["v0"] = np.ones_like(s["v0"])
+    s["material"] = dict(s["material"], law=0)
+    g = gpu(s).step(3000)
+    with pytest.raises(LdpmError) as ei:
+        g.sync()
+    assert ei.value.status == LDPM_ERR_UNSTABLE
+
+
+def test_mixed_precision_accuracy_tension():
+    """FP32 facets / FP64 state against the FP64 oracle: peak nominal stress
+    within 1 % and energy-balance error within 1e-3."""
+    s = tension_small()
+    o = O.Oracle(s)
+    g = gpu(s, precision="mixed")
+    prog = s["meta"]["load_prog"]
+    so, sg = [], []
+    for _ in range(12):
+        o.step(100)
+        g.step(100)
+        so.append(o.reaction_sum(prog))
+        sg.append(g.reaction(prog))
+    so, sg = np.array(so), np.array(sg)
+    peak_err = abs(sg.max() - so.max()) / abs(so.max())
+    eg = g.energy()
+    eo = o.energies()
+    print("mixed: peak stress error", peak_err, "energy err", eg["err"], "oracle", eo["err"])
+    assert peak_err <= 1e-2
+    assert eg["err"] <= 1e-3
+    assert abs(eg["W_int"] - eo["W_int"]) <= 1e-2 * abs(eo["W_int"])
