@@ -95,6 +95,10 @@ def lib():
     """Load libldpm.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch's HIP runtime must be the one the library binds to (one
+        # runtime per process; streams and allocations are shared with it):
+        # load it first so libamdhip64.so.7 resolves to the copy in memory.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2603_13190_amd/build.py")
         L = C.CDLL(LIB_PATH)
