@@ -165,13 +165,19 @@ void ora_facet_law(const ora_mat *p, double len, const double e[3], const double
     const double eN = e[0], eM = e[1], eL = e[2];
     if (eN > 0.0) {
         /* ---- fracturing behaviour (e_N > 0) ---- */
-        double eff = sqrt(eN * eN + al * (eM * eM + eL * eL));            /* e */
-        double eff_old = sqrt(e_old[0] * e_old[0] + al * (e_old[1] * e_old[1] + e_old[2] * e_old[2]));
-        double t_eff_old = sqrt(t_old[0] * t_old[0] + (t_old[1] * t_old[1] + t_old[2] * t_old[2]) / al);
+        /* effective strain e = sqrt(e_N^2 + alpha (e_M^2 + e_L^2)), evaluated
+         * with hypot so that tiny strains cannot underflow to e = 0 while
+         * e_N > 0 (the definition gives e >= e_N > 0)                      */
+        const double sa = sqrt(al);
+        double eTs = sa * hypot(eM, eL);                                   /* sqrt(alpha) e_T */
+        double eff = hypot(eN, eTs);                                       /* e */
+        double eff_old = hypot(e_old[0], sa * hypot(e_old[1], e_old[2]));
+        double t_eff_old = hypot(t_old[0], hypot(t_old[1], t_old[2]) / sa);
         /* coupling variable: tan(omega) = e_N / sqrt(alpha (e_M^2 + e_L^2)) */
-        double omega = atan2(eN, sqrt(al * (eM * eM + eL * eL)));
+        double omega = atan2(eN, eTs);
         double sn = eN / eff;
-        double cs2 = al * (eM * eM + eL * eL) / (eff * eff);
+        double cw = eTs / eff;
+        double cs2 = cw * cw;
         double rst2 = p->r_st * p->r_st;
         /* strength limit sigma_0(omega), rationalised */
         double sigma0 = 2.0 * p->sigma_t / (sn + sqrt(sn * sn + 4.0 * al * cs2 / rst2));

@@ -20,6 +20,31 @@ __device__ __forceinline__ double d_atan2(double y, double x) { return atan2(y, 
 __device__ __forceinline__ float d_atan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double d_pow(double x, double y) { return pow(x, y); }
 __device__ __forceinline__ float d_pow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double d_frexp(double x, int* e) { return frexp(x, e); }
+__device__ __forceinline__ float d_frexp(float x, int* e) { return frexpf(x, e); }
+__device__ __forceinline__ double d_ldexp(double x, int e) { return ldexp(x, e); }
+__device__ __forceinline__ float d_ldexp(float x, int e) { return ldexpf(x, e); }
+__device__ __forceinline__ double d_abs(double x) { return fabs(x); }
+__device__ __forceinline__ float d_abs(float x) { return fabsf(x); }
+
+// |(a, b, c)| weighted as sqrt(a^2 + w (b^2 + c^2)), returned as the scaled
+// value sv, its square sv2 and the exponent ex with value = sv * 2^ex.  The
+// power-of-two rescaling is exact, so in the normal range the result equals
+// the plain formula bit for bit; it only prevents squares of tiny strains
+// from underflowing (e = 0 while e_N > 0).
+template <typename R>
+__device__ __forceinline__ void scaled_norm(R a, R b, R c, R w, R& sa, R& sbc2, R& sv, R& sv2, int& ex)
+{
+    R mx = d_abs(a);
+    mx = d_abs(b) > mx ? d_abs(b) : mx;
+    mx = d_abs(c) > mx ? d_abs(c) : mx;
+    (void)d_frexp(mx, &ex);
+    sa = d_ldexp(a, -ex);
+    const R sb = d_ldexp(b, -ex), sc = d_ldexp(c, -ex);
+    sbc2 = sb * sb + sc * sc;
+    sv2 = sa * sa + w * sbc2;
+    sv = d_sqrt(sv2);
+}
 
 // Material constants in the facet precision, derived once on the host.
 template <typename R>
@@ -49,26 +74,30 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
     if (eN > R(0)) {
         // ---- fracturing behaviour ----
         const R al = p.alpha;
-        const R eT2 = eM * eM + eL * eL;
-        const R eff2 = eN * eN + al * eT2;
-        const R eff = d_sqrt(eff2);
+        R sN, sT2, seff, seff2;
+        int ex;
+        scaled_norm(eN, eM, eL, al, sN, sT2, seff, seff2, ex);
+        const R eff = d_ldexp(seff, ex);
         const R o0 = eN - de[0], o1 = eM - de[1], o2 = eL - de[2];
-        const R effo = d_sqrt(o0 * o0 + al * (o1 * o1 + o2 * o2));
+        R so0, soT2, seffo, seffo2;
+        int exo;
+        scaled_norm(o0, o1, o2, al, so0, soT2, seffo, seffo2, exo);
+        const R effo = d_ldexp(seffo, exo);
         // effective-strain increment without cancellation:
         // e^2 - e_old^2 = sum w_i de_i (e_i + e_old_i)
         const R num = de[0] * (eN + o0) + al * (de[1] * (eM + o1) + de[2] * (eL + o2));
         const R den = eff + effo;
         const R deff = den > R(0) ? num / den : R(0);
         const R teo = d_sqrt(t[0] * t[0] + (t[1] * t[1] + t[2] * t[2]) * p.inv_alpha);
-        const R sn = eN / eff;
-        const R cs2 = al * eT2 / eff2;
+        const R sn = sN / seff;
+        const R cs2 = al * sT2 / seff2;
         const R sigma0 = R(2) * p.sigma_t / (sn + d_sqrt(sn * sn + p.c4 * cs2));
         const R e0 = sigma0 / p.E0;
         const R em = emax > eff ? emax : eff;
         const R over = em - e0;
         R sbt = sigma0;
         if (over > R(0)) {  // softening started: exp(-H0 <e_max - e0> / sigma0)
-            const R omega = d_atan2(eN, d_sqrt(al * eT2));
+            const R omega = d_atan2(sN, d_sqrt(al * sT2));
             const R Ht = R(2) * p.E0 / (p.l_t / len - R(1));
             const R H0 = p.Hs_over_alpha + (Ht - p.Hs_over_alpha) * d_pow(p.two_over_pi * omega, p.n_t);
             sbt = sigma0 * d_exp(-H0 * over / sigma0);

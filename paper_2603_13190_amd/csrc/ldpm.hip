@@ -3,8 +3,9 @@
 // Data layout in HBM (structure of arrays):
 //   particles  x0[3][N], q[6][N], v[6][N], mass[N], inertia[3][N],
 //              dof mode/program/scale [6][N], fext[6][N], w_ext[N], w_kin[N],
-//              incidence CSR: ptr[N+1], slot[4T] (slot = 4 tet + local node)
-//   tets       nodes[4][T], w_int[T], contributions [4T][6] (per tet-node)
+//              incidence CSR: ptr[N+1]; tet-node (t, a) sits at pos[4t+a]
+//   tets       nodes[4][T], pos[4T], w_int[T],
+//              contributions [4T][6] per tet-node, stored in incidence order
 //   facets     cI[3][F], area[F], rec[F] (edge-frame id | local I,J code),
 //              history t[3][F], e_max[F]                (FP64 or FP32)
 //   edge frames n[3][E], m[3][E], len[E]  (deduplicated (n, m, len) triples)
@@ -18,9 +19,10 @@
 //              moments c x (A P t) (eq. balance), internal-work increment;
 //              the 6 facets touching each tet node are summed in LDS in a
 //              fixed order, so each tet writes 4 x 6 numbers instead of 12 x 9.
-//   k_particle one lane per particle: gathers its tet-node contributions in
-//              ascending tetrahedron order (CSR, no atomics), adds applied and
-//              body forces, leapfrog update in FP64, reactions, energies.
+//   k_particle 16 lanes per particle: gathers its tet-node contributions,
+//              stored contiguously in ascending tetrahedron order (no
+//              atomics), adds applied and body forces, leapfrog update in
+//              FP64 (one lane per DoF), reactions, energies.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -99,7 +101,6 @@ struct ParticleArgs {
     double* __restrict__ wext;           // [N]
     double* __restrict__ wkin;           // [N]
     const int32_t* __restrict__ ptr;     // [N+1]
-    const int32_t* __restrict__ slot;    // [4T]
     const int64_t* __restrict__ prog_off;
     const double* __restrict__ prog_t;
     const double* __restrict__ prog_v;
@@ -123,6 +124,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap)
 
 template <typename R, int LAW, int TB>
 __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
+                                                   const int32_t* __restrict__ pos,
                                                    R* __restrict__ contrib, double* __restrict__ wint,
                                                    double dt, int first, int remap)
 {
@@ -142,6 +144,31 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
     const int64_t tet0 = blk * TB;
     const int64_t T = na.T, N = na.N;
+
+    // ---- facet data for lane tid, issued before the node gather so that
+    //      both latencies overlap ----
+    const int ftl = tid / 12;
+    const bool fvalid = (tid < NF) && (tet0 + ftl < T);
+    const int64_t f = (tet0 + ftl) * 12 + (tid % 12);
+    int32_t rc = 0;
+    R n0 = 0, n1 = 0, n2 = 0, m0 = 0, m1 = 0, m2 = 0, len = 1, cI0 = 0, cI1 = 0, cI2 = 0, A = 0;
+    R tv[3] = {R(0), R(0), R(0)};
+    R emx = R(0);
+    if (fvalid) {
+        const int64_t F = fa.F, E = fa.E;
+        rc = fa.rec[f];
+        const int64_t r = rc & 0x0fffffff;
+        n0 = fa.en[r]; n1 = fa.en[E + r]; n2 = fa.en[2 * E + r];
+        m0 = fa.em[r]; m1 = fa.em[E + r]; m2 = fa.em[2 * E + r];
+        len = fa.elen[r];
+        cI0 = fa.cI[f]; cI1 = fa.cI[F + f]; cI2 = fa.cI[2 * F + f];
+        A = fa.area[f];
+        tv[0] = fa.ht[f]; tv[1] = fa.ht[F + f]; tv[2] = fa.ht[2 * F + f];
+        if (LAW != 0) emx = fa.hemax[f];
+    }
+    // output position (incidence order) of the tet-node sums of phase D
+    int32_t opos = 0;
+    if (tid < NS && tet0 + (tid >> 2) < T) opos = pos[(tet0 + (tid >> 2)) * 4 + (tid & 3)];
 
     // ---- A: stage the 4 nodes of each tet (slot a*TB + tl) ----
     if (tid < NS) {
@@ -189,27 +216,16 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
 
     // ---- C: one lane per facet ----
     if (tid < NF) {
-        const int tl = tid / 12;
-        const int64_t tt = tet0 + tl;
+        const int tl = ftl;
         double wk = 0.0;
         uint8_t code = 0xff;
-        if (tt < T) {
-            const int64_t f = tt * 12 + (tid % 12);
-            const int64_t F = fa.F, E = fa.E;
-            const int32_t rc = fa.rec[f];
+        if (fvalid) {
+            const int64_t F = fa.F;
             const int aI = (rc >> 28) & 3, aJ = (rc >> 30) & 3;
-            const int64_t r = rc & 0x0fffffff;
             code = (uint8_t)(aI | (aJ << 2));
             const int sI = aI * TB + tl, sJ = aJ * TB + tl;
-            const R n0 = fa.en[r], n1 = fa.en[E + r], n2 = fa.en[2 * E + r];
-            const R m0 = fa.em[r], m1 = fa.em[E + r], m2 = fa.em[2 * E + r];
-            const R len = fa.elen[r];
             const R l0 = n1 * m2 - n2 * m1, l1 = n2 * m0 - n0 * m2, l2 = n0 * m1 - n1 * m0;
-            const R cI0 = fa.cI[f], cI1 = fa.cI[F + f], cI2 = fa.cI[2 * F + f];
             const R cJ0 = cI0 - len * n0, cJ1 = cI1 - len * n1, cJ2 = cI2 - len * n2;
-            const R A = fa.area[f];
-            R tv[3] = {fa.ht[f], fa.ht[F + f], fa.ht[2 * F + f]};
-            R emx = LAW != 0 ? fa.hemax[f] : R(0);
             const R told0 = tv[0], told1 = tv[1], told2 = tv[2];
             // displacement jump [[u]] = u_J + th_J x c^J - u_I - th_I x c^I
             // (translation difference in FP64, rotation terms in R)
@@ -242,10 +258,10 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
                 de[1] = e[1];
                 de[2] = e[2];
             } else {      // q^n - q^{n-1} = dt v^{n-1/2}
-                const R s = (R)dt * il;
-                de[0] = (n0 * dv[0] + n1 * dv[1] + n2 * dv[2]) * s;
-                de[1] = (m0 * dv[0] + m1 * dv[1] + m2 * dv[2]) * s;
-                de[2] = (l0 * dv[0] + l1 * dv[1] + l2 * dv[2]) * s;
+                const R sc = (R)dt * il;
+                de[0] = (n0 * dv[0] + n1 * dv[1] + n2 * dv[2]) * sc;
+                de[1] = (m0 * dv[0] + m1 * dv[1] + m2 * dv[2]) * sc;
+                de[2] = (l0 * dv[0] + l1 * dv[1] + l2 * dv[2]) * sc;
             }
             const R eV = (R)((s_ev[tl] + s_ev[TB + tl] + s_ev[2 * TB + tl] + s_ev[3 * TB + tl]) / 3.0);
             facet_law<R, LAW>(mat, len, e, de, eV, tv, emx);
@@ -275,7 +291,8 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
     }
     __syncthreads();
 
-    // ---- D: per tet node, sum its 6 facets in ascending local order ----
+    // ---- D: per tet node, sum its 6 facets in ascending local order and
+    //      write the sum at the node's incidence position ----
     if (tid < NS) {
         const int tl = tid >> 2, a = tid & 3;
         const int64_t tt = tet0 + tl;
@@ -299,7 +316,7 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
                     }
                 }
             }
-            R* out = contrib + (tt * 4 + a) * 6;
+            R* out = contrib + (int64_t)opos * 6;
 #pragma unroll
             for (int c = 0; c < 6; c++) out[c] = acc[c];
             if (a == 0) {
@@ -332,34 +349,51 @@ __device__ __forceinline__ double prog_eval(const ParticleArgs& pa, int32_t p, d
     return pa.prog_v[b - 1];
 }
 
+// PG lanes per particle: lane l sums incidences ptr[I] + l, + PG, ... of the
+// contributions stored in incidence order; an xor butterfly (commutative, so
+// every lane ends with the same bits) completes the sum; lane d < 6 then
+// advances DoF d.  The grouping is fixed, so results do not depend on the
+// block size.
+constexpr int PG = 16;
+
 template <typename R>
 __global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __restrict__ contrib,
                                                    int64_t n, double dt)
 {
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t I = gt / PG;
+    const int lane = (int)(gt % PG);
     const int64_t N = pa.N;
-    if (I >= N) return;
+    if (I >= N) return;  // whole groups of PG lanes leave together
     double f[6] = {0, 0, 0, 0, 0, 0};
     const int32_t s0 = pa.ptr[I], s1 = pa.ptr[I + 1];
-    for (int32_t s = s0; s < s1; s++) {
-        const R* c = contrib + (int64_t)pa.slot[s] * 6;
+    for (int32_t s = s0 + lane; s < s1; s += PG) {
+        const R* c = contrib + (int64_t)s * 6;
 #pragma unroll
         for (int d = 0; d < 6; d++) f[d] += (double)c[d];
     }
-    const double time = (double)n * dt;
-    const double h = (n == 0) ? 0.5 * dt : dt;
-    const double t_half = ((double)n + 0.5) * dt;
+#pragma unroll
+    for (int off = PG / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 6; d++) f[d] += __shfl_xor(f[d], off, PG);
+    }
     double wk = 0.0, dwe = 0.0;
     bool bad = false;
+    if (lane < 6) {
+        const int d = lane;
+        double fd = f[0];
 #pragma unroll
-    for (int d = 0; d < 6; d++) {
+        for (int k = 1; k < 6; k++) fd = (d == k) ? f[k] : fd;
+        const double time = (double)n * dt;
+        const double h = (n == 0) ? 0.5 * dt : dt;
+        const double t_half = ((double)n + 0.5) * dt;
         const int64_t id = d * N + I;
         const double M = d < 3 ? pa.mass[I] : pa.inertia[(d - 3) * N + I];
         double applied = pa.body ? pa.body[id] : 0.0;
         const int32_t pg = pa.prog[id];
         const uint8_t md = pa.mode[id];
         if (md == 0 && pg >= 0) applied += pa.scale[id] * prog_eval(pa, pg, time);
-        const double fnet = f[d] + applied;
+        const double fnet = fd + applied;
         const double vold = pa.v[id];
         double vnew, Fd;
         if (md == 0) {
@@ -370,16 +404,25 @@ __global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __r
             const double R_ = M * (vnew - vold) / h - fnet;  // reaction
             Fd = applied + R_;
         }
-        if (n > 0) dwe += 0.5 * (pa.fext[id] + Fd) * (dt * vold);
+        if (n > 0) dwe = 0.5 * (pa.fext[id] + Fd) * (dt * vold);
         const double vb = (n == 0) ? vold : 0.5 * (vold + vnew);
-        wk += 0.5 * M * vb * vb;
+        wk = 0.5 * M * vb * vb;
         pa.fext[id] = Fd;
         pa.v[id] = vnew;
         pa.q[id] += dt * vnew;
-        bad |= !isfinite(vnew);
+        bad = !isfinite(vnew);
     }
-    pa.wext[I] += dwe;
-    pa.wkin[I] = wk;
+    // energies of the particle: DoFs summed in order 0..5 by lane 0
+    double wks = 0.0, dws = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        wks += __shfl(wk, d, PG);
+        dws += __shfl(dwe, d, PG);
+    }
+    if (lane == 0) {
+        pa.wext[I] += dws;
+        pa.wkin[I] = wks;
+    }
     if (bad) pa.flag[0] = 1;
 }
 
@@ -454,7 +497,7 @@ struct ldpm_system {
     // device pointers
     double *x0, *q, *v, *mass, *inertia, *scale, *body, *fext, *wext, *wkin, *wint;
     uint8_t* mode;
-    int32_t *prog, *ptr, *slot, *tet, *rec, *flag;
+    int32_t *prog, *ptr, *pos, *tet, *rec, *flag;
     int64_t* prog_off;
     double *prog_t, *prog_v, *red;
     void *cI, *area, *en, *em, *elen, *ht, *hemax, *contrib;
@@ -555,7 +598,7 @@ static void launch_facet_t(ldpm_system* s, int first)
     const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
     const int64_t nb = (s->T + TB - 1) / TB;
     hipLaunchKernelGGL((k_facet<R, LAW, TB>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
-                       (R*)s->contrib, s->wint, s->dt, first, s->launch.xcd_remap);
+                       s->pos, (R*)s->contrib, s->wint, s->dt, first, s->launch.xcd_remap);
 }
 
 template <typename R, int LAW>
@@ -582,10 +625,10 @@ static void launch_facet(ldpm_system* s, int first)
 static void launch_particle(ldpm_system* s, int64_t n)
 {
     ParticleArgs pa{s->q,     s->v,    s->mass, s->inertia, s->mode,     s->prog,   s->scale,
-                    s->body,  s->fext, s->wext, s->wkin,    s->ptr,      s->slot,   s->prog_off,
+                    s->body,  s->fext, s->wext, s->wkin,    s->ptr,      s->prog_off,
                     s->prog_t, s->prog_v, s->flag, s->N};
     const int th = s->launch.particle_threads;
-    const unsigned nb = (unsigned)((s->N + th - 1) / th);
+    const unsigned nb = (unsigned)((s->N * PG + th - 1) / th);
     if (s->prec == LDPM_PREC_MIXED)
         hipLaunchKernelGGL(k_particle<float>, dim3(nb), dim3(th), 0, s->stream, pa, (const float*)s->contrib, n,
                            s->dt);
@@ -730,14 +773,18 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
             emS[c * E + r] = em[3 * r + c];
         }
     // ---- incidence CSR: slots 4t+a in ascending order ----
-    std::vector<int32_t> ptr(N + 1, 0), slot(4 * T);
+    std::vector<int32_t> ptr(N + 1, 0), slot(4 * T), pos(4 * T);
     for (int64_t t = 0; t < T; t++)
         for (int a = 0; a < 4; a++) ptr[d->tet_nodes[a * T + t] + 1]++;
     for (int64_t i = 0; i < N; i++) ptr[i + 1] += ptr[i];
     {
         std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
         for (int64_t t = 0; t < T; t++)
-            for (int a = 0; a < 4; a++) slot[fill[d->tet_nodes[a * T + t]]++] = (int32_t)(4 * t + a);
+            for (int a = 0; a < 4; a++) {
+                const int32_t at = fill[d->tet_nodes[a * T + t]]++;
+                slot[at] = (int32_t)(4 * t + a);
+                pos[4 * t + a] = at;
+            }
     }
     // ---- body force: constant generalised force V_I b, V_I r_I x b ----
     std::vector<double> body;
@@ -765,7 +812,8 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     const size_t o_body = body.empty() ? 0 : cv.take<double>(6 * N);
     const size_t o_fext = cv.take<double>(6 * N), o_wext = cv.take<double>(N), o_wkin = cv.take<double>(N);
     const size_t o_wint = cv.take<double>(T), o_mode = cv.take<uint8_t>(6 * N), o_prog = cv.take<int32_t>(6 * N);
-    const size_t o_ptr = cv.take<int32_t>(N + 1), o_slot = cv.take<int32_t>(4 * T), o_tet = cv.take<int32_t>(4 * T);
+    const size_t o_ptr = cv.take<int32_t>(N + 1), o_tet = cv.take<int32_t>(4 * T);
+    const size_t o_pos = cv.take<int32_t>(4 * T);
     const size_t o_rec = cv.take<int32_t>(F), o_flag = cv.take<int32_t>(4);
     const size_t o_poff = cv.take<int64_t>(nP + 1), o_pt = cv.take<double>(npts + 1), o_pv = cv.take<double>(npts + 1);
     const size_t o_red = cv.take<double>(8);
@@ -813,7 +861,8 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->body = body.empty() ? nullptr : (double*)(B + o_body);
     s->fext = (double*)(B + o_fext); s->wext = (double*)(B + o_wext); s->wkin = (double*)(B + o_wkin);
     s->wint = (double*)(B + o_wint); s->mode = (uint8_t*)(B + o_mode); s->prog = (int32_t*)(B + o_prog);
-    s->ptr = (int32_t*)(B + o_ptr); s->slot = (int32_t*)(B + o_slot); s->tet = (int32_t*)(B + o_tet);
+    s->ptr = (int32_t*)(B + o_ptr); s->tet = (int32_t*)(B + o_tet);
+    s->pos = (int32_t*)(B + o_pos);
     s->rec = (int32_t*)(B + o_rec); s->flag = (int32_t*)(B + o_flag);
     s->prog_off = (int64_t*)(B + o_poff); s->prog_t = (double*)(B + o_pt); s->prog_v = (double*)(B + o_pv);
     s->red = (double*)(B + o_red);
@@ -851,7 +900,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     CK(H2D(s->mode, d->dof_mode, 6 * N));
     CK(H2D(s->prog, d->dof_prog, 6 * N * 4));
     CK(H2D(s->ptr, ptr.data(), (N + 1) * 4));
-    CK(H2D(s->slot, slot.data(), 4 * T * 4));
+    CK(H2D(s->pos, pos.data(), 4 * T * 4));
     CK(H2D(s->tet, d->tet_nodes, 4 * T * 4));
     CK(H2D(s->rec, rec.data(), F * 4));
     std::vector<int64_t> po(nP + 1, 0);
@@ -1031,16 +1080,16 @@ ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
     o->law = s->law;
     const double N = (double)s->N, T = (double)s->T, F = (double)s->F, E = (double)s->E;
     // facet kernel: each array touched once per launch
-    //   facets: rec 4 + cI 3R + area R + history (t 3R + e_max R) read and written
-    //   edge frames 7R per frame; tets: nodes 16 B, w_int 16 B (r+w), contributions 24R
-    //   particles: x0, q, v (15 doubles)
+    //   facets: rec 4 B + cI 3R + area R + history (t 3R + e_max R) read and written
+    //   edge frames 7R per frame; tets: nodes 16 B, pos 16 B, w_int 16 B (r+w),
+    //   contributions written 24R; particles: x0, q, v read (15 doubles)
     const double hist = (s->law == 1 ? 4.0 : 3.0) * rb;
-    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + hist + 3.0 * rb) + E * 7.0 * rb + T * (16.0 + 16.0 + 24.0 * rb) +
+    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + 2.0 * hist) + E * 7.0 * rb + T * (16.0 + 16.0 + 16.0 + 24.0 * rb) +
                             N * 15.0 * 8.0;
-    // particle kernel: contributions 24R per tet, slot ids, ptr, particle state
-    //   q, v, fext (r+w 6 doubles each), mass + inertia 4 doubles, scale 6, prog 6x4,
-    //   mode 6, w_ext r+w, w_kin w
-    o->particle_kernel_bytes = T * (24.0 * rb + 16.0) + N * (4.0 + 6 * 8 * 2 * 3 + 4 * 8 + 6 * 8 + 24 + 6 + 16 + 8);
+    // particle kernel: contributions 24R per tet read; per particle ptr 4 B,
+    //   q, v, fext read + written (3 x 6 x 16 B), mass + inertia 32 B, scale 48 B,
+    //   prog 24 B, mode 6 B, w_ext r+w 16 B, w_kin 8 B
+    o->particle_kernel_bytes = T * 24.0 * rb + N * (4.0 + 288.0 + 32.0 + 48.0 + 24.0 + 6.0 + 16.0 + 8.0);
     o->device_bytes = s->arena_bytes;
     return LDPM_OK;
 }
