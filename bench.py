@@ -77,6 +77,23 @@ def accuracy_run(sysd, precision, total, every, launch=None):
     return hist, en, g
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    from paper_2603_13190_amd import rocprof_summary as RS
+    path = os.path.join(ROOT, "profiles", f"facet_kernel_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha1") != RS.source_sha1():
+        return None
+    k = rec["kernels"].get("void " + kernel) or rec["kernels"].get(kernel)
+    if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +108,8 @@ def main():
     ap.add_argument("--particle-threads", type=int, default=256)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="bytes of a plain device copy to run (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the explicit LDPM step is measured on a single "
@@ -139,6 +158,10 @@ def main():
                      "alg_bytes_per_launch": info["facet_kernel_bytes"],
                      "avg_launch_us": favg * 1e3, "particle_kernel_avg_us": pavg * 1e3},
     }
+
+    traffic = measured_traffic(args.workload, "k_facet<double, 1, %d>" % args.tets_per_block)
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic
 
     # ---- mixed precision, timed ----
     if not args.no_mixed:
@@ -190,6 +213,15 @@ def main():
                                "sample": f"{n} explicit steps (steps 5..{5 + n}) of the same workload, "
                                          f"{el:.1f} s, OpenMP over facets and particles"}
         log(f"cpu oracle: {F * n / el:.4e} facet-upd/s on {cores} threads")
+
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 4} bytes x 3")
 
     print(json.dumps(out), flush=True)
 

@@ -49,7 +49,7 @@ __device__ __forceinline__ void scaled_norm(R a, R b, R c, R w, R& sa, R& sbc2, 
 // Material constants in the facet precision, derived once on the host.
 template <typename R>
 struct MatDev {
-    R E0, alpha, aE0, inv_alpha;
+    R E0, alpha, aE0, inv_alpha, inv_E0;
     R sigma_t, l_t, c4;          // c4 = 4 alpha / r_st^2
     R n_t, Hs_over_alpha, k_t;
     R sigma_c0, Hc0, Hc1, kc1, kc2, eV0, ec0, ec1, Ed, beta;
@@ -89,10 +89,11 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
         const R den = eff + effo;
         const R deff = den > R(0) ? num / den : R(0);
         const R teo = d_sqrt(t[0] * t[0] + (t[1] * t[1] + t[2] * t[2]) * p.inv_alpha);
-        const R sn = sN / seff;
-        const R cs2 = al * sT2 / seff2;
+        const R inv = R(1) / seff;
+        const R sn = sN * inv;
+        const R cs2 = al * sT2 * (inv * inv);
         const R sigma0 = R(2) * p.sigma_t / (sn + d_sqrt(sn * sn + p.c4 * cs2));
-        const R e0 = sigma0 / p.E0;
+        const R e0 = sigma0 * p.inv_E0;
         const R em = emax > eff ? emax : eff;
         const R over = em - e0;
         R sbt = sigma0;
@@ -102,7 +103,7 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
             const R H0 = p.Hs_over_alpha + (Ht - p.Hs_over_alpha) * d_pow(p.two_over_pi * omega, p.n_t);
             sbt = sigma0 * d_exp(-H0 * over / sigma0);
         }
-        const R etr = p.k_t * (em - sbt / p.E0);
+        const R etr = p.k_t * (em - sbt * p.inv_E0);
         R ttr;
         if (teo > R(0)) {
             ttr = teo + p.E0 * deff;
@@ -115,7 +116,7 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
         }
         R te = ttr < R(0) ? R(0) : ttr;
         te = te > sbt ? sbt : te;
-        const R r = te / eff;
+        const R r = d_ldexp(te * inv, -ex);  // te / eff
         t[0] = r * eN;
         t[1] = al * r * eM;
         t[2] = al * r * eL;

@@ -24,6 +24,7 @@
 //              atomics), adds applied and body forces, leapfrog update in
 //              FP64 (one lane per DoF), reactions, energies.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <math.h>
 #include <stdint.h>
@@ -88,6 +89,33 @@ struct NodeArgs {
     int64_t N, T;
 };
 
+// Piecewise-linear time programs (constant beyond their end points).  The
+// facet kernel's first block evaluates every program at t_n and t_{n+1/2}
+// into progv[2p], progv[2p+1]; the particle kernel of the same step reads them.
+struct ProgArgs {
+    const int64_t* __restrict__ off;  // [P+1]
+    const double* __restrict__ t;
+    const double* __restrict__ v;
+    double* __restrict__ val;         // [2P]
+    int64_t P;
+};
+
+__device__ __forceinline__ double prog_at(const ProgArgs& pr, int64_t p, double time)
+{
+    const int64_t a = pr.off[p], b = pr.off[p + 1];
+    if (b <= a) return 0.0;
+    if (time <= pr.t[a]) return pr.v[a];
+    for (int64_t i = a; i + 1 < b; i++) {
+        const double t1 = pr.t[i + 1];
+        if (time <= t1) {
+            const double t0 = pr.t[i];
+            const double w = (time - t0) / (t1 - t0);
+            return pr.v[i] + w * (pr.v[i + 1] - pr.v[i]);
+        }
+    }
+    return pr.v[b - 1];
+}
+
 struct ParticleArgs {
     double* __restrict__ q;           // [6][N]
     double* __restrict__ v;           // [6][N]
@@ -101,9 +129,7 @@ struct ParticleArgs {
     double* __restrict__ wext;           // [N]
     double* __restrict__ wkin;           // [N]
     const int32_t* __restrict__ ptr;     // [N+1]
-    const int64_t* __restrict__ prog_off;
-    const double* __restrict__ prog_t;
-    const double* __restrict__ prog_v;
+    const double* __restrict__ progv;    // [2P] program values of this step
     int32_t* __restrict__ flag;
     int64_t N;
 };
@@ -126,8 +152,9 @@ template <typename R, int LAW, int TB>
 __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
                                                    const int32_t* __restrict__ pos,
                                                    R* __restrict__ contrib, double* __restrict__ wint,
-                                                   double dt, int first, int remap)
+                                                   ProgArgs pr, int64_t step, double dt, int remap)
 {
+    const int first = step == 0;
     constexpr int NS = 4 * TB;   // node slots per block
     constexpr int NF = 12 * TB;  // facets per block
     __shared__ double s_x[3][NS];
@@ -166,9 +193,21 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
         tv[0] = fa.ht[f]; tv[1] = fa.ht[F + f]; tv[2] = fa.ht[2 * F + f];
         if (LAW != 0) emx = fa.hemax[f];
     }
-    // output position (incidence order) of the tet-node sums of phase D
+    // output position (incidence order) of the tet-node sums of phase D, and
+    // the tet's accumulated internal work
     int32_t opos = 0;
-    if (tid < NS && tet0 + (tid >> 2) < T) opos = pos[(tet0 + (tid >> 2)) * 4 + (tid & 3)];
+    double wacc = 0.0;
+    if (tid < NS && tet0 + (tid >> 2) < T) {
+        opos = pos[(tet0 + (tid >> 2)) * 4 + (tid & 3)];
+        if ((tid & 3) == 0) wacc = wint[tet0 + (tid >> 2)];
+    }
+    if (blockIdx.x == 0) {
+        const double tn = (double)step * dt, th = ((double)step + 0.5) * dt;
+        for (int64_t p = tid; p < pr.P; p += blockDim.x) {
+            pr.val[2 * p] = prog_at(pr, p, tn);
+            pr.val[2 * p + 1] = prog_at(pr, p, th);
+        }
+    }
 
     // ---- A: stage the 4 nodes of each tet (slot a*TB + tl) ----
     if (tid < NS) {
@@ -323,7 +362,7 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
                 double w = 0.0;
 #pragma unroll
                 for (int j = 0; j < 12; j++) w += s_w[tl * 12 + j];
-                wint[tt] += w;
+                wint[tt] = wacc + w;
             }
         }
     }
@@ -332,23 +371,6 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
 // ---------------------------------------------------------------------------
 // particle kernel
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double prog_eval(const ParticleArgs& pa, int32_t p, double time)
-{
-    if (p < 0) return 0.0;
-    const int64_t a = pa.prog_off[p], b = pa.prog_off[p + 1];
-    if (b <= a) return 0.0;
-    if (time <= pa.prog_t[a]) return pa.prog_v[a];
-    for (int64_t i = a; i + 1 < b; i++) {
-        const double t1 = pa.prog_t[i + 1];
-        if (time <= t1) {
-            const double t0 = pa.prog_t[i];
-            const double w = (time - t0) / (t1 - t0);
-            return pa.prog_v[i] + w * (pa.prog_v[i + 1] - pa.prog_v[i]);
-        }
-    }
-    return pa.prog_v[b - 1];
-}
-
 // PG lanes per particle: lane l sums incidences ptr[I] + l, + PG, ... of the
 // contributions stored in incidence order; an xor butterfly (commutative, so
 // every lane ends with the same bits) completes the sum; lane d < 6 then
@@ -365,51 +387,54 @@ __global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __r
     const int lane = (int)(gt % PG);
     const int64_t N = pa.N;
     if (I >= N) return;  // whole groups of PG lanes leave together
+    // per-DoF data of lane d < 6, loaded before the gather
+    const int d = lane < 6 ? lane : 0;
+    const int64_t id = d * N + I;
+    const double M = d < 3 ? pa.mass[I] : pa.inertia[(d - 3) * N + I];
+    const double bodyf = pa.body ? pa.body[id] : 0.0;
+    const int32_t pg = pa.prog[id];
+    const uint8_t md = pa.mode[id];
+    const double scl = pa.scale[id];
+    const double vold = pa.v[id];
+    const double fold = pa.fext[id];
+    const double qold = pa.q[id];
     double f[6] = {0, 0, 0, 0, 0, 0};
     const int32_t s0 = pa.ptr[I], s1 = pa.ptr[I + 1];
     for (int32_t s = s0 + lane; s < s1; s += PG) {
         const R* c = contrib + (int64_t)s * 6;
 #pragma unroll
-        for (int d = 0; d < 6; d++) f[d] += (double)c[d];
+        for (int k = 0; k < 6; k++) f[k] += (double)c[k];
     }
 #pragma unroll
     for (int off = PG / 2; off > 0; off >>= 1) {
 #pragma unroll
-        for (int d = 0; d < 6; d++) f[d] += __shfl_xor(f[d], off, PG);
+        for (int k = 0; k < 6; k++) f[k] += __shfl_xor(f[k], off, PG);
     }
     double wk = 0.0, dwe = 0.0;
     bool bad = false;
     if (lane < 6) {
-        const int d = lane;
         double fd = f[0];
 #pragma unroll
         for (int k = 1; k < 6; k++) fd = (d == k) ? f[k] : fd;
-        const double time = (double)n * dt;
         const double h = (n == 0) ? 0.5 * dt : dt;
-        const double t_half = ((double)n + 0.5) * dt;
-        const int64_t id = d * N + I;
-        const double M = d < 3 ? pa.mass[I] : pa.inertia[(d - 3) * N + I];
-        double applied = pa.body ? pa.body[id] : 0.0;
-        const int32_t pg = pa.prog[id];
-        const uint8_t md = pa.mode[id];
-        if (md == 0 && pg >= 0) applied += pa.scale[id] * prog_eval(pa, pg, time);
+        double applied = bodyf;
+        if (md == 0 && pg >= 0) applied += scl * pa.progv[2 * pg];
         const double fnet = fd + applied;
-        const double vold = pa.v[id];
         double vnew, Fd;
         if (md == 0) {
             vnew = vold + h * fnet / M;
             Fd = applied;
         } else {
-            vnew = (pg >= 0) ? pa.scale[id] * prog_eval(pa, pg, t_half) : 0.0;
+            vnew = (pg >= 0) ? scl * pa.progv[2 * pg + 1] : 0.0;
             const double R_ = M * (vnew - vold) / h - fnet;  // reaction
             Fd = applied + R_;
         }
-        if (n > 0) dwe = 0.5 * (pa.fext[id] + Fd) * (dt * vold);
+        if (n > 0) dwe = 0.5 * (fold + Fd) * (dt * vold);
         const double vb = (n == 0) ? vold : 0.5 * (vold + vnew);
         wk = 0.5 * M * vb * vb;
         pa.fext[id] = Fd;
         pa.v[id] = vnew;
-        pa.q[id] += dt * vnew;
+        pa.q[id] = qold + dt * vnew;
         bad = !isfinite(vnew);
     }
     // energies of the particle: DoFs summed in order 0..5 by lane 0
@@ -499,7 +524,7 @@ struct ldpm_system {
     uint8_t* mode;
     int32_t *prog, *ptr, *pos, *tet, *rec, *flag;
     int64_t* prog_off;
-    double *prog_t, *prog_v, *red;
+    double *prog_t, *prog_v, *progv, *red;
     void *cI, *area, *en, *em, *elen, *ht, *hemax, *contrib;
     int64_t n_prog_pts = 0, n_prog = 0;
     MatDev<double> matd;
@@ -529,6 +554,7 @@ MatDev<R> make_mat(const ldpm_material& m)
     p.alpha = (R)al;
     p.aE0 = (R)(al * E0);
     p.inv_alpha = (R)(1.0 / al);
+    p.inv_E0 = (R)(1.0 / E0);
     p.sigma_t = (R)m.sigma_t;
     p.l_t = (R)m.l_t;
     p.c4 = (R)(4.0 * al / (m.r_st * m.r_st));
@@ -589,52 +615,67 @@ size_t rbytes(int prec) { return prec == LDPM_PREC_MIXED ? 4 : 8; }
 
 }  // namespace
 
+// Kernel launches.  With events (ev0, ev1) the launch is made with
+// hipExtLaunchKernelGGL, whose start/stop events are timestamped by the
+// dispatch itself (the kernel's own duration, as a profiler reports it).
 template <typename R, int LAW, int TB>
-static void launch_facet_t(ldpm_system* s, int first)
+static void launch_facet_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
     NodeArgs na{s->tet, s->x0, s->q, s->v, s->N, s->T};
     FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->en, (const R*)s->em,
                     (const R*)s->elen, (R*)s->ht, (R*)s->hemax, s->F, s->E};
+    ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
     const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
     const int64_t nb = (s->T + TB - 1) / TB;
-    hipLaunchKernelGGL((k_facet<R, LAW, TB>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
-                       s->pos, (R*)s->contrib, s->wint, s->dt, first, s->launch.xcd_remap);
+    if (ev0)
+        hipExtLaunchKernelGGL((k_facet<R, LAW, TB>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, ev0, ev1, 0,
+                              na, fa, mat, (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt,
+                              s->launch.xcd_remap);
+    else
+        hipLaunchKernelGGL((k_facet<R, LAW, TB>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
+                           (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt, s->launch.xcd_remap);
 }
 
 template <typename R, int LAW>
-static void launch_facet_l(ldpm_system* s, int first)
+static void launch_facet_l(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (s->launch.tets_per_block) {
-    case 32: launch_facet_t<R, LAW, 32>(s, first); break;
-    case 64: launch_facet_t<R, LAW, 64>(s, first); break;
-    default: launch_facet_t<R, LAW, 16>(s, first); break;
+    case 32: launch_facet_t<R, LAW, 32>(s, ev0, ev1); break;
+    case 64: launch_facet_t<R, LAW, 64>(s, ev0, ev1); break;
+    default: launch_facet_t<R, LAW, 16>(s, ev0, ev1); break;
     }
 }
 
-static void launch_facet(ldpm_system* s, int first)
+static void launch_facet(ldpm_system* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     if (s->prec == LDPM_PREC_MIXED) {
-        if (s->law == 0) launch_facet_l<float, 0>(s, first);
-        else launch_facet_l<float, 1>(s, first);
+        if (s->law == 0) launch_facet_l<float, 0>(s, ev0, ev1);
+        else launch_facet_l<float, 1>(s, ev0, ev1);
     } else {
-        if (s->law == 0) launch_facet_l<double, 0>(s, first);
-        else launch_facet_l<double, 1>(s, first);
+        if (s->law == 0) launch_facet_l<double, 0>(s, ev0, ev1);
+        else launch_facet_l<double, 1>(s, ev0, ev1);
     }
 }
 
-static void launch_particle(ldpm_system* s, int64_t n)
+template <typename R>
+static void launch_particle_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    ParticleArgs pa{s->q,     s->v,    s->mass, s->inertia, s->mode,     s->prog,   s->scale,
-                    s->body,  s->fext, s->wext, s->wkin,    s->ptr,      s->prog_off,
-                    s->prog_t, s->prog_v, s->flag, s->N};
+    ParticleArgs pa{s->q,    s->v,    s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
+                    s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N};
     const int th = s->launch.particle_threads;
     const unsigned nb = (unsigned)((s->N * PG + th - 1) / th);
-    if (s->prec == LDPM_PREC_MIXED)
-        hipLaunchKernelGGL(k_particle<float>, dim3(nb), dim3(th), 0, s->stream, pa, (const float*)s->contrib, n,
-                           s->dt);
+    if (ev0)
+        hipExtLaunchKernelGGL(k_particle<R>, dim3(nb), dim3(th), 0, s->stream, ev0, ev1, 0, pa,
+                              (const R*)s->contrib, s->step, s->dt);
     else
-        hipLaunchKernelGGL(k_particle<double>, dim3(nb), dim3(th), 0, s->stream, pa, (const double*)s->contrib, n,
+        hipLaunchKernelGGL(k_particle<R>, dim3(nb), dim3(th), 0, s->stream, pa, (const R*)s->contrib, s->step,
                            s->dt);
+}
+
+static void launch_particle(ldpm_system* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+{
+    if (s->prec == LDPM_PREC_MIXED) launch_particle_t<float>(s, ev0, ev1);
+    else launch_particle_t<double>(s, ev0, ev1);
 }
 
 extern "C" {
@@ -817,6 +858,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     const size_t o_rec = cv.take<int32_t>(F), o_flag = cv.take<int32_t>(4);
     const size_t o_poff = cv.take<int64_t>(nP + 1), o_pt = cv.take<double>(npts + 1), o_pv = cv.take<double>(npts + 1);
     const size_t o_red = cv.take<double>(8);
+    const size_t o_progv = cv.take<double>(2 * nP + 2);
     cv.off = (cv.off + 255) & ~size_t(255);
     const size_t o_cI = cv.off; cv.off += 3 * F * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
@@ -866,6 +908,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->rec = (int32_t*)(B + o_rec); s->flag = (int32_t*)(B + o_flag);
     s->prog_off = (int64_t*)(B + o_poff); s->prog_t = (double*)(B + o_pt); s->prog_v = (double*)(B + o_pv);
     s->red = (double*)(B + o_red);
+    s->progv = (double*)(B + o_progv);
     s->cI = B + o_cI; s->area = B + o_area; s->en = B + o_en; s->em = B + o_em; s->elen = B + o_el;
     s->ht = B + o_ht; s->hemax = B + o_hem; s->contrib = B + o_con;
 
@@ -956,8 +999,8 @@ ldpm_status ldpm_step(ldpm_system* s, int64_t n_steps)
     if (!s) return fail(LDPM_ERR_ARG, "null handle");
     if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
     for (int64_t i = 0; i < n_steps; i++) {
-        launch_facet(s, s->step == 0 ? 1 : 0);
-        launch_particle(s, s->step);
+        launch_facet(s);
+        launch_particle(s);
         s->step++;
     }
     hipError_t e = hipGetLastError();
@@ -969,25 +1012,30 @@ ldpm_status ldpm_step_profiled(ldpm_system* s, int64_t n_steps, double* facet_ms
 {
     if (!s || !facet_ms || !particle_ms) return fail(LDPM_ERR_ARG, "null argument");
     if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
-    hipEvent_t ev[3];
-    for (int i = 0; i < 3; i++) HIP_TRY(hipEventCreate(&ev[i]));
+    constexpr int CH = 128;  // steps per chunk of events
+    std::vector<hipEvent_t> ev(4 * CH);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     double fsum = 0.0, psum = 0.0;
     hipError_t e = hipSuccess;
-    for (int64_t i = 0; i < n_steps && e == hipSuccess; i++) {
-        e = hipEventRecord(ev[0], s->stream);
-        launch_facet(s, s->step == 0 ? 1 : 0);
-        if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
-        launch_particle(s, s->step);
-        s->step++;
-        if (e == hipSuccess) e = hipEventRecord(ev[2], s->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
-        float a = 0.f, b = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[1], ev[2]);
-        fsum += a;
-        psum += b;
+    for (int64_t done = 0; done < n_steps && e == hipSuccess;) {
+        const int k = (int)std::min<int64_t>(CH, n_steps - done);
+        for (int i = 0; i < k; i++) {
+            launch_facet(s, ev[4 * i], ev[4 * i + 1]);
+            launch_particle(s, ev[4 * i + 2], ev[4 * i + 3]);
+            s->step++;
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventSynchronize(ev[4 * (k - 1) + 3]);
+        for (int i = 0; i < k && e == hipSuccess; i++) {
+            float a = 0.f, b = 0.f;
+            e = hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]);
+            fsum += a;
+            psum += b;
+        }
+        done += k;
     }
-    for (int i = 0; i < 3; i++) (void)hipEventDestroy(ev[i]);
+    for (auto& x : ev) (void)hipEventDestroy(x);
     if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "profiled step failed: %s", hipGetErrorString(e));
     *facet_ms = fsum;
     *particle_ms = psum;

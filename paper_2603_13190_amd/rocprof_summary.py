@@ -1,0 +1,116 @@
+"""Summarise rocprofv3 output into the short text/JSON records kept in profiles/.
+
+  python -m paper_2603_13190_amd.rocprof_summary stats  <kernel_stats.csv> <out.txt> <command...>
+  python -m paper_2603_13190_amd.rocprof_summary pmc    <fetch_counter_collection.csv>
+         <write_counter_collection.csv> <out.json> <calibration_bytes> <command...>
+
+The PMC mode reads FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the facet
+kernels and of the calibration copy kernel (a plain device-to-device copy of
+a known number of bytes), scales the facet-kernel counters by
+known_bytes / counter_of_copy, and records them with the SHA-1 of the kernel
+sources, so that a later benchmark reports the traffic only while the kernel
+is unchanged.
+"""
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", "ldpm.hip"), os.path.join(HERE, "csrc", "law.hpp")]
+
+
+def source_sha1():
+    h = hashlib.sha1()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name):
+    name = name.split("(")[0]
+    return name[:90]
+
+
+def stats(csv_path, out_path, command):
+    rows = _rows(csv_path)
+    lines = [f"command: {command}", f"source: {os.path.basename(csv_path)} (rocprofv3 --kernel-trace --stats)",
+             f"kernel sources sha1: {source_sha1()}", "",
+             f"{'kernel':60s} {'calls':>8s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in rows:
+        name = r.get("Name") or r.get("KernelName") or r.get("Kernel_Name")
+        calls = int(float(r.get("Calls", 0)))
+        avg = float(r.get("AverageNs", 0)) / 1e3
+        mn = float(r.get("MinNs", 0)) / 1e3
+        mx = float(r.get("MaxNs", 0)) / 1e3
+        tot = float(r.get("TotalDurationNs", 0)) / 1e6
+        pct = float(r.get("Percentage", 0))
+        lines.append(f"{_short(name):60s} {calls:8d} {avg:10.2f} {mn:10.2f} {mx:10.2f} {tot:10.2f} {pct:6.2f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counter_by_kernel(path, counter):
+    vals = defaultdict(list)
+    for r in _rows(path):
+        cn = r.get("Counter_Name") or r.get("CounterName")
+        if cn != counter:
+            continue
+        name = r.get("Kernel_Name") or r.get("KernelName") or r.get("Name")
+        vals[_short(name)].append(float(r.get("Counter_Value") or r.get("CounterValue")))
+    return vals
+
+
+def pmc(fetch_csv, write_csv, out_path, calib_bytes, command):
+    fetch = _counter_by_kernel(fetch_csv, "FETCH_SIZE")
+    write = _counter_by_kernel(write_csv, "WRITE_SIZE")
+    calib = float(calib_bytes)
+
+    def copy_kernel(d):
+        cands = [k for k in d if "copy" in k.lower() or "elementwise" in k.lower()]
+        # the calibration copy is the largest-traffic copy kernel
+        return max(cands, key=lambda k: max(d[k])) if cands else None
+
+    kf, kw = copy_kernel(fetch), copy_kernel(write)
+    f_scale = calib / (max(fetch[kf]) * 1024.0) if kf else None
+    w_scale = calib / (max(write[kw]) * 1024.0) if kw else None
+    out = {"command": command, "kernel_sources_sha1": source_sha1(),
+           "calibration": {"bytes": calib, "fetch_kernel": kf, "write_kernel": kw,
+                           "fetch_KiB": max(fetch[kf]) if kf else None,
+                           "write_KiB": max(write[kw]) if kw else None,
+                           "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernels": {}}
+    for k in sorted(set(fetch) | set(write)):
+        if not k.startswith("void k_") and not k.startswith("k_") and "k_facet" not in k and "k_particle" not in k:
+            continue
+        fv, wv = fetch.get(k, []), write.get(k, [])
+        fa = sum(fv) / len(fv) * 1024.0 if fv else None
+        wa = sum(wv) / len(wv) * 1024.0 if wv else None
+        out["kernels"][k] = {
+            "dispatches": max(len(fv), len(wv)),
+            "fetch_bytes_raw": fa, "write_bytes_raw": wa,
+            "fetch_bytes": fa * f_scale if (fa is not None and f_scale) else None,
+            "write_bytes": wa * w_scale if (wa is not None and w_scale) else None,
+        }
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "stats":
+        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif mode == "pmc":
+        pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], " ".join(sys.argv[6:]))
+    else:
+        raise SystemExit(__doc__)
