@@ -37,12 +37,17 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def timed_run(sysd, precision, warmup, steps, launch=None):
+def timed_run(sysd, precision, warmup, steps, launch=None, tune=None):
     import torch
     from paper_2603_13190_amd.ldpm import System
     g = System(sysd, precision=precision)
     if launch:
         g.set_launch(**launch)
+    if tune:
+        best, us, trials = g.autotune(steps_per_trial=tune)
+        g.tuned = dict(best=best, us_per_step=us, trials=len(trials),
+                       worst_us_per_step=max(t[1] for t in trials) if trials else us)
+        log(f"autotune ({precision}): best {best} at {us:.2f} us/step over {len(trials)} shapes")
     g.step(warmup)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -94,6 +99,49 @@ def measured_traffic(workload, kernel):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
+def batched_case(args, tune):
+    """64 seeded sliding-platen compression cubes (edges U(50, 100) mm, d 4-8)
+    batched into one system; throughput of a window of steps in FP64 and
+    mixed precision, per-specimen energy errors and mixed-vs-FP64 peak
+    reaction over the window."""
+    from paper_2603_13190_amd import specimen as S
+    import numpy as np
+    t = time.perf_counter()
+    b = S.batch_sliding_compression(64, seed=0)
+    gen_s = time.perf_counter() - t
+    F = b["meta"]["F"]
+    nsp = b["meta"]["n_specimens"]
+    rec = {"workload": "64 x unconfined compression, sliding platens, edge U(50,100) mm, d 4-8 mm, "
+                       "strain rate 2.5e-2 /s, seeds 0..63",
+           "particles": b["meta"]["N"], "tets": b["meta"]["T"], "facets": F,
+           "specimen_facets_min": min(b["meta"]["specimen_F"]),
+           "specimen_facets_max": max(b["meta"]["specimen_F"]),
+           "dt": b["dt"], "steps": args.batch_steps, "generation_s": gen_s}
+    peaks = {}
+    for prec in ("fp64", "mixed"):
+        g, ms, _ = timed_run(b, prec, 50, args.batch_steps, None, tune)
+        v = F * args.batch_steps / (ms * 1e-3)
+        errs = [g.energy(i)["err"] for i in range(nsp)]
+        peaks[prec] = np.array([g.reaction(i) for i in range(nsp)])
+        g.set_launch(**dict(g.get_launch(), persistent=0))
+        info = g.info()
+        fms, _ = g.step_profiled(200)
+        favg = fms / 200
+        rec[prec] = {"value": v, "ms_per_step": ms / args.batch_steps,
+                     "energy_err_max": float(max(errs)),
+                     "launch": getattr(g, "tuned", {}).get("best") if getattr(g, "tuned", None) else None,
+                     "facet_kernel_avg_us": favg * 1e3,
+                     "facet_kernel_GBs": info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9,
+                     "facet_kernel_frac_hbm": info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        g.close()
+        log(f"batched {prec}: {v:.4e} facet-upd/s, facet kernel {favg * 1e3:.1f} us "
+            f"({rec[prec]['facet_kernel_GBs']:.0f} GB/s)")
+    rec["mixed"]["speedup_vs_fp64"] = rec["mixed"]["value"] / rec["fp64"]["value"]
+    rec["mixed"]["reaction_err_vs_fp64_max"] = float(
+        np.max(np.abs(peaks["mixed"] - peaks["fp64"]) / np.maximum(np.abs(peaks["fp64"]), 1e-30)))
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +155,10 @@ def main():
     ap.add_argument("--tets-per-block", type=int, default=16)
     ap.add_argument("--particle-threads", type=int, default=256)
     ap.add_argument("--xcd-remap", type=int, default=1)
+    ap.add_argument("--no-tune", action="store_true", help="keep the given launch shape")
+    ap.add_argument("--tune-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-specimen batched case")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="bytes of a plain device copy to run (counter calibration)")
@@ -127,7 +179,10 @@ def main():
     log(f"workload {args.workload}: N={N} T={T} F={F} dt={sysd['dt']:.4e} steps={steps} warmup={args.warmup}")
 
     # ---- FP64, timed ----
-    g64, ms64, wall64 = timed_run(sysd, "fp64", args.warmup, steps, launch)
+    tune = None if args.no_tune else args.tune_steps
+    g64, ms64, wall64 = timed_run(sysd, "fp64", args.warmup, steps, launch, tune)
+    if tune:
+        launch = g64.get_launch()
     info = g64.info()
     en64 = g64.energy()
     v64 = F * steps / (ms64 * 1e-3)
@@ -135,6 +190,8 @@ def main():
         f"energy err {en64['err']:.3e}")
 
     # ---- roofline of the dominant (facet) kernel, HIP events per launch ----
+    # (per-kernel timing always runs the facet and particle kernels separately)
+    g64.set_launch(**dict(launch, persistent=0))
     fms, pms = g64.step_profiled(args.profile_steps)
     favg = fms / args.profile_steps
     pavg = pms / args.profile_steps
@@ -150,7 +207,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "particles": N, "tets": T,
                    "facets": F, "edge_frames": info["n_edges"], "dt": sysd["dt"],
-                   "trajectory_steps": args.warmup + steps, "launch": launch},
+                   "trajectory_steps": args.warmup + steps, "launch": launch,
+                   "autotune": getattr(g64, "tuned", None)},
         "energy_balance_err": en64["err"],
         "roofline": {"bound": "hbm", "kernel": "k_facet<double,1,%d>" % args.tets_per_block,
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -165,7 +223,8 @@ def main():
 
     # ---- mixed precision, timed ----
     if not args.no_mixed:
-        gmx, msmx, _ = timed_run(sysd, "mixed", args.warmup, steps, launch)
+        gmx, msmx, _ = timed_run(sysd, "mixed", args.warmup, steps, None, tune or None)
+        gmx.set_launch(**dict(gmx.get_launch(), persistent=0))
         imx = gmx.info()
         fms2, _ = gmx.step_profiled(args.profile_steps)
         favg2 = fms2 / args.profile_steps
@@ -195,6 +254,10 @@ def main():
                 "W_int_rel_err_vs_fp64": abs(emx["W_int"] - e64["W_int"]) / abs(e64["W_int"]),
             })
             log(f"peak stress fp64 {peak64:.4f} MPa, mixed {peakmx:.4f} MPa; energy err mixed {emx['err']:.2e}")
+
+    # ---- batched: 64 uneven specimens in one system (window of steps) ----
+    if not args.no_batch:
+        out["batched"] = batched_case(args, tune)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----
     if not args.no_cpu:

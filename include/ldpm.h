@@ -202,16 +202,37 @@ typedef struct {
 ldpm_status ldpm_get_info(ldpm_system *s, ldpm_info *out);
 
 /* Launch configuration of the step: tetrahedra per facet block (16, 32 or
- * 64), threads per particle block (64..1024, multiple of 64), and whether
- * the facet kernel's launch order is interleaved across the chip's XCDs.
- * Results do not depend on it (bitwise).                                   */
+ * 64), threads per particle block (64..1024, multiple of 64), whether the
+ * facet kernel's tiles are remapped so that each XCD (own L2) works on a
+ * contiguous range, and whether ldpm_step runs as one persistent
+ * cooperative launch per chunk of steps (facet and particle phases separated
+ * by grid barriers) instead of two kernels per step.  Results do not depend
+ * on it (bitwise).                                                          */
 typedef struct {
     int32_t tets_per_block;
     int32_t particle_threads;
     int32_t xcd_remap;
+    int32_t persistent;
 } ldpm_launch;
 ldpm_status ldpm_set_launch(ldpm_system *s, const ldpm_launch *cfg);
 ldpm_status ldpm_get_launch(ldpm_system *s, ldpm_launch *out);
+
+/* Autotuner: times every launch shape (tets_per_block x particle_threads x
+ * xcd_remap for two kernels per step, and tets_per_block for the persistent
+ * launch) for steps_per_trial steps on the live system, keeps the
+ * fastest and returns it (best, best_us = microseconds per step).  The
+ * dynamic state is saved before the trials and restored afterwards (a
+ * temporary device buffer of the state's size is allocated), so the
+ * trajectory is unchanged.  Choices are cached for the process per (GPU
+ * architecture, system shape); a cache hit returns with *n_trials = 0.
+ * trials (may be NULL) receives up to max_trials timings.                   */
+typedef struct {
+    ldpm_launch launch;
+    double us_per_step;
+} ldpm_tune_trial;
+ldpm_status ldpm_autotune(ldpm_system *s, int32_t steps_per_trial, ldpm_launch *best,
+                          double *best_us, ldpm_tune_trial *trials, int32_t max_trials,
+                          int32_t *n_trials);
 
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);

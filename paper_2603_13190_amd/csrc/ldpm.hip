@@ -148,11 +148,13 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap)
     return x * qn + (x < r ? x : r) + k;
 }
 
+// One tile of TB tetrahedra (block-wide: every thread of a 12 TB block calls
+// it together).  do_prog: this block also evaluates the time programs.
 template <typename R, int LAW, int TB>
-__global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
-                                                   const int32_t* __restrict__ pos,
-                                                   R* __restrict__ contrib, double* __restrict__ wint,
-                                                   ProgArgs pr, int64_t step, double dt, int remap)
+__device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const NodeArgs& na, const FacetArgs<R>& fa,
+                                           const MatDev<R>& mat, const int32_t* __restrict__ pos,
+                                           R* __restrict__ contrib, double* __restrict__ wint,
+                                           const ProgArgs& pr, int64_t step, double dt)
 {
     const int first = step == 0;
     constexpr int NS = 4 * TB;   // node slots per block
@@ -168,7 +170,6 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
     __shared__ uint8_t s_code[NF];
 
     const int tid = threadIdx.x;
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x, remap);
     const int64_t tet0 = blk * TB;
     const int64_t T = na.T, N = na.N;
 
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
         opos = pos[(tet0 + (tid >> 2)) * 4 + (tid & 3)];
         if ((tid & 3) == 0) wacc = wint[tet0 + (tid >> 2)];
     }
-    if (blockIdx.x == 0) {
+    if (do_prog) {
         const double tn = (double)step * dt, th = ((double)step + 0.5) * dt;
         for (int64_t p = tid; p < pr.P; p += blockDim.x) {
             pr.val[2 * p] = prog_at(pr, p, tn);
@@ -368,6 +369,16 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
     }
 }
 
+template <typename R, int LAW, int TB>
+__global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
+                                                   const int32_t* __restrict__ pos,
+                                                   R* __restrict__ contrib, double* __restrict__ wint,
+                                                   ProgArgs pr, int64_t step, double dt, int remap)
+{
+    facet_tile<R, LAW, TB>(xcd_block(blockIdx.x, gridDim.x, remap), blockIdx.x == 0, na, fa, mat, pos, contrib,
+                           wint, pr, step, dt);
+}
+
 // ---------------------------------------------------------------------------
 // particle kernel
 // ---------------------------------------------------------------------------
@@ -378,15 +389,16 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
 // block size.
 constexpr int PG = 16;
 
+// Particle I = gt / PG, lane gt % PG (gt: a global lane index; groups of PG
+// lanes are aligned within a wave and take the branch together).
 template <typename R>
-__global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __restrict__ contrib,
-                                                   int64_t n, double dt)
+__device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& pa, const R* __restrict__ contrib,
+                                               int64_t n, double dt)
 {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t I = gt / PG;
     const int lane = (int)(gt % PG);
     const int64_t N = pa.N;
-    if (I >= N) return;  // whole groups of PG lanes leave together
+    if (I >= N) return;
     // per-DoF data of lane d < 6, loaded before the gather
     const int d = lane < 6 ? lane : 0;
     const int64_t id = d * N + I;
@@ -449,6 +461,76 @@ __global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __r
         pa.wkin[I] = wks;
     }
     if (bad) pa.flag[0] = 1;
+}
+
+template <typename R>
+__global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __restrict__ contrib,
+                                                   int64_t n, double dt)
+{
+    particle_group<R>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, pa, contrib, n, dt);
+}
+
+// ---------------------------------------------------------------------------
+// persistent multi-step kernel: n steps in one cooperative launch, the facet
+// and particle phases separated by grid barriers.  Co-residency of every
+// block is guaranteed by the cooperative launch; the barrier still gives up
+// after a bounded wait (flagging an error) so that no wave can spin forever.
+// ---------------------------------------------------------------------------
+struct GridSync {
+    unsigned* count;  // arrivals at the current barrier
+    unsigned* gen;    // barrier generation
+    int32_t* flag;    // [1]: barrier timeout (error flag word 1)
+};
+
+__device__ __forceinline__ bool grid_barrier(const GridSync& g, unsigned nblocks)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // release this block's writes to the whole device
+        const unsigned gen0 = __hip_atomic_load(g.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(g.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        int ok = 1;
+        if (arrived == nblocks) {
+            __hip_atomic_store(g.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(g.gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1l << 24)) {  // ~seconds: never reached when co-resident
+                    g.flag[1] = 1;
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();  // acquire the other blocks' writes
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <typename R, int LAW, int TB>
+__global__ __launch_bounds__(12 * TB) void k_persist(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
+                                                     const int32_t* __restrict__ pos, R* __restrict__ contrib,
+                                                     double* __restrict__ wint, ProgArgs pr, ParticleArgs pa,
+                                                     GridSync gs, int64_t step0, int64_t nsteps, double dt)
+{
+    const int64_t nb = (na.T + TB - 1) / TB;
+    const unsigned G = gridDim.x;
+    const int64_t lanes = pa.N * PG;
+    for (int64_t i = 0; i < nsteps; i++) {
+        const int64_t n = step0 + i;
+        for (int64_t blk = blockIdx.x; blk < nb; blk += G)
+            facet_tile<R, LAW, TB>(blk, blk == 0, na, fa, mat, pos, contrib, wint, pr, n, dt);
+        if (!grid_barrier(gs, G)) return;
+        for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < lanes; gt += (int64_t)G * blockDim.x)
+            particle_group<R>(gt, pa, contrib, n, dt);
+        if (!grid_barrier(gs, G)) return;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -516,13 +598,16 @@ struct ldpm_system {
     void* arena = nullptr;
     size_t arena_bytes = 0;
     void (*dev_free)(void*, void*) = nullptr;
+    void* (*dev_alloc)(size_t, void*) = nullptr;
     void* alloc_ctx = nullptr;
     int device = 0;
-    ldpm_launch launch{16, 256, 1};
+    ldpm_launch launch{16, 256, 1, 0};
+    int n_cu = 0;
     // device pointers
     double *x0, *q, *v, *mass, *inertia, *scale, *body, *fext, *wext, *wkin, *wint;
     uint8_t* mode;
     int32_t *prog, *ptr, *pos, *tet, *rec, *flag;
+    unsigned* bar;
     int64_t* prog_off;
     double *prog_t, *prog_v, *progv, *red;
     void *cI, *area, *en, *em, *elen, *ht, *hemax, *contrib;
@@ -676,6 +761,75 @@ static void launch_particle(ldpm_system* s, hipEvent_t ev0 = nullptr, hipEvent_t
 {
     if (s->prec == LDPM_PREC_MIXED) launch_particle_t<float>(s, ev0, ev1);
     else launch_particle_t<double>(s, ev0, ev1);
+}
+
+// Persistent launch: chunks of at most PERSIST_CHUNK steps per cooperative
+// launch, grid = the number of blocks that fit on the chip at once.
+constexpr int64_t PERSIST_CHUNK = 1024;
+
+template <typename R, int LAW, int TB>
+static hipError_t launch_persist_t(ldpm_system* s, int64_t nsteps)
+{
+    auto kern = k_persist<R, LAW, TB>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 12 * TB, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+    const int64_t nb = (s->T + TB - 1) / TB;
+    const int64_t np = (s->N * PG + 12 * TB - 1) / (12 * TB);
+    int64_t G = (int64_t)per_cu * s->n_cu;
+    G = std::min<int64_t>(G, std::max<int64_t>(nb, np));
+    NodeArgs na{s->tet, s->x0, s->q, s->v, s->N, s->T};
+    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->en, (const R*)s->em,
+                    (const R*)s->elen, (R*)s->ht, (R*)s->hemax, s->F, s->E};
+    ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
+    ParticleArgs pa{s->q,    s->v,    s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
+                    s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N};
+    GridSync gs{s->bar, s->bar + 1, s->flag};
+    MatDev<R> mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
+    const int32_t* pos = s->pos;
+    R* contrib = (R*)s->contrib;
+    double* wint = s->wint;
+    double dt = s->dt;
+    for (int64_t done = 0; done < nsteps;) {
+        int64_t k = std::min<int64_t>(PERSIST_CHUNK, nsteps - done);
+        int64_t step0 = s->step;
+        void* args[] = {&na, &fa, &mat, &pos, &contrib, &wint, &pr, &pa, &gs, &step0, &k, &dt};
+        e = hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(12 * TB), args, 0, s->stream);
+        if (e != hipSuccess) return e;
+        s->step += k;
+        done += k;
+    }
+    return hipSuccess;
+}
+
+template <typename R, int LAW>
+static hipError_t launch_persist_l(ldpm_system* s, int64_t n)
+{
+    switch (s->launch.tets_per_block) {
+    case 32: return launch_persist_t<R, LAW, 32>(s, n);
+    case 64: return launch_persist_t<R, LAW, 64>(s, n);
+    default: return launch_persist_t<R, LAW, 16>(s, n);
+    }
+}
+
+static hipError_t launch_persist(ldpm_system* s, int64_t n)
+{
+    if (s->prec == LDPM_PREC_MIXED)
+        return s->law == 0 ? launch_persist_l<float, 0>(s, n) : launch_persist_l<float, 1>(s, n);
+    return s->law == 0 ? launch_persist_l<double, 0>(s, n) : launch_persist_l<double, 1>(s, n);
+}
+
+// n steps in the configured launch shape
+static hipError_t run_steps(ldpm_system* s, int64_t n)
+{
+    if (s->launch.persistent) return launch_persist(s, n);
+    for (int64_t i = 0; i < n; i++) {
+        launch_facet(s);
+        launch_particle(s);
+        s->step++;
+    }
+    return hipGetLastError();
 }
 
 extern "C" {
@@ -855,7 +1009,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     const size_t o_wint = cv.take<double>(T), o_mode = cv.take<uint8_t>(6 * N), o_prog = cv.take<int32_t>(6 * N);
     const size_t o_ptr = cv.take<int32_t>(N + 1), o_tet = cv.take<int32_t>(4 * T);
     const size_t o_pos = cv.take<int32_t>(4 * T);
-    const size_t o_rec = cv.take<int32_t>(F), o_flag = cv.take<int32_t>(4);
+    const size_t o_rec = cv.take<int32_t>(F), o_flag = cv.take<int32_t>(4), o_bar = cv.take<unsigned>(4);
     const size_t o_poff = cv.take<int64_t>(nP + 1), o_pt = cv.take<double>(npts + 1), o_pv = cv.take<double>(npts + 1);
     const size_t o_red = cv.take<double>(8);
     const size_t o_progv = cv.take<double>(2 * nP + 2);
@@ -883,11 +1037,13 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->poff = poff; s->toff = toff; s->dt = d->dt;
     s->stream = (hipStream_t)d->stream;
     s->dev_free = d->dev_alloc ? d->dev_free : nullptr;
+    s->dev_alloc = d->dev_alloc;
     s->alloc_ctx = d->alloc_ctx;
     s->n_prog = nP; s->n_prog_pts = npts;
     s->matd = make_mat<double>(mat);
     s->matf = make_mat<float>(mat);
     (void)hipGetDevice(&s->device);
+    (void)hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, s->device);
     void* base = nullptr;
     if (d->dev_alloc) {
         base = d->dev_alloc(total, d->alloc_ctx);
@@ -905,7 +1061,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->wint = (double*)(B + o_wint); s->mode = (uint8_t*)(B + o_mode); s->prog = (int32_t*)(B + o_prog);
     s->ptr = (int32_t*)(B + o_ptr); s->tet = (int32_t*)(B + o_tet);
     s->pos = (int32_t*)(B + o_pos);
-    s->rec = (int32_t*)(B + o_rec); s->flag = (int32_t*)(B + o_flag);
+    s->rec = (int32_t*)(B + o_rec); s->flag = (int32_t*)(B + o_flag); s->bar = (unsigned*)(B + o_bar);
     s->prog_off = (int64_t*)(B + o_poff); s->prog_t = (double*)(B + o_pt); s->prog_v = (double*)(B + o_pv);
     s->red = (double*)(B + o_red);
     s->progv = (double*)(B + o_progv);
@@ -968,6 +1124,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     std::vector<double> zT(T, 0.0);
     CK(H2D(s->wint, (is && is->w_int) ? is->w_int : zT.data(), T * 8));
     CK(hipMemsetAsync(s->flag, 0, 16, s->stream));
+    CK(hipMemsetAsync(s->bar, 0, 16, s->stream));
     CK(hipMemsetAsync(s->contrib, 0, 4 * T * 6 * rb, s->stream));
 #undef CK
     // initial kinetic energy per specimen, particle order then DoF order
@@ -998,12 +1155,7 @@ ldpm_status ldpm_step(ldpm_system* s, int64_t n_steps)
 {
     if (!s) return fail(LDPM_ERR_ARG, "null handle");
     if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
-    for (int64_t i = 0; i < n_steps; i++) {
-        launch_facet(s);
-        launch_particle(s);
-        s->step++;
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = run_steps(s, n_steps);
     if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return LDPM_OK;
 }
@@ -1046,9 +1198,10 @@ ldpm_status ldpm_sync(ldpm_system* s)
 {
     if (!s) return fail(LDPM_ERR_ARG, "null handle");
     HIP_TRY(hipStreamSynchronize(s->stream));
-    int32_t flag = 0;
-    HIP_TRY(hipMemcpy(&flag, s->flag, 4, hipMemcpyDeviceToHost));
-    if (flag) return fail(LDPM_ERR_UNSTABLE, "non-finite velocity: the step is unstable");
+    int32_t flag[2] = {0, 0};
+    HIP_TRY(hipMemcpy(flag, s->flag, 8, hipMemcpyDeviceToHost));
+    if (flag[1]) return fail(LDPM_ERR_DEVICE, "persistent launch: a grid barrier timed out");
+    if (flag[0]) return fail(LDPM_ERR_UNSTABLE, "non-finite velocity: the step is unstable");
     return LDPM_OK;
 }
 
@@ -1151,6 +1304,141 @@ ldpm_status ldpm_set_launch(ldpm_system* s, const ldpm_launch* c)
         return fail(LDPM_ERR_ARG, "particle_threads must be a multiple of 64 in [64, 1024]");
     s->launch = *c;
     s->launch.xcd_remap = c->xcd_remap ? 1 : 0;
+    s->launch.persistent = c->persistent ? 1 : 0;
+    return LDPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: times every launch shape on the live system and keeps the
+// fastest.  The dynamic state is saved before the trials and restored after,
+// and results do not depend on the launch shape, so tuning never changes the
+// trajectory.  Choices are cached per (GPU architecture, system shape).
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+    std::string arch;
+    int64_t N, T, F, E, nspec;
+    int32_t prec, law;
+    bool operator==(const TuneKey& o) const
+    {
+        return arch == o.arch && N == o.N && T == o.T && F == o.F && E == o.E && nspec == o.nspec &&
+               prec == o.prec && law == o.law;
+    }
+};
+struct TuneEntry {
+    TuneKey key;
+    ldpm_launch best;
+    double us;
+};
+std::vector<TuneEntry> g_tune_cache;
+
+struct Region {
+    void* p;
+    size_t bytes;
+};
+
+std::vector<Region> dynamic_regions(ldpm_system* s)
+{
+    const size_t rb = rbytes(s->prec);
+    const size_t N = (size_t)s->N, T = (size_t)s->T, F = (size_t)s->F;
+    return {{s->q, 6 * N * 8}, {s->v, 6 * N * 8},   {s->fext, 6 * N * 8}, {s->wext, N * 8},
+            {s->wkin, N * 8},  {s->wint, T * 8},    {s->ht, 3 * F * rb},  {s->hemax, F * rb}};
+}
+}  // namespace
+
+ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* best, double* best_us,
+                          ldpm_tune_trial* trials, int32_t max_trials, int32_t* n_trials)
+{
+    if (!s) return fail(LDPM_ERR_ARG, "null handle");
+    if (steps_per_trial <= 0) return fail(LDPM_ERR_ARG, "steps_per_trial must be positive");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, s->device));
+    TuneKey key{prop.gcnArchName, s->N, s->T, s->F, s->E, s->nspec, s->prec, s->law};
+    for (const auto& t : g_tune_cache)
+        if (t.key == key) {
+            s->launch = t.best;
+            if (best) *best = t.best;
+            if (best_us) *best_us = t.us;
+            if (n_trials) *n_trials = 0;
+            return LDPM_OK;
+        }
+    // save the dynamic state
+    auto regs = dynamic_regions(s);
+    size_t total = 0;
+    for (auto& r : regs) total += (r.bytes + 255) & ~size_t(255);
+    void* snap = nullptr;
+    if (s->dev_alloc) snap = s->dev_alloc(total, s->alloc_ctx);
+    else if (hipMalloc(&snap, total) != hipSuccess) snap = nullptr;
+    if (!snap) return fail(LDPM_ERR_ALLOC, "autotune: cannot allocate %zu bytes for the state snapshot", total);
+    auto copy_all = [&](bool save) -> hipError_t {
+        size_t off = 0;
+        for (auto& r : regs) {
+            char* sp = (char*)snap + off;
+            hipError_t e = save ? hipMemcpyAsync(sp, r.p, r.bytes, hipMemcpyDeviceToDevice, s->stream)
+                                : hipMemcpyAsync(r.p, sp, r.bytes, hipMemcpyDeviceToDevice, s->stream);
+            if (e != hipSuccess) return e;
+            off += (r.bytes + 255) & ~size_t(255);
+        }
+        return hipSuccess;
+    };
+    const int64_t step0 = s->step;
+    const ldpm_launch keep = s->launch;
+    hipError_t e = copy_all(true);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    const int tbs[3] = {16, 32, 64};
+    const int pts[4] = {64, 128, 256, 512};
+    std::vector<ldpm_launch> cands;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 4; j++)
+            for (int rm = 0; rm < 2; rm++) cands.push_back(ldpm_launch{tbs[i], pts[j], rm, 0});
+    for (int i = 0; i < 3; i++) cands.push_back(ldpm_launch{tbs[i], 256, 0, 1});
+    double best_t = 1e300;
+    ldpm_launch best_l = keep;
+    int32_t nt = 0;
+    for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ci++) {
+        s->launch = cands[ci];
+        e = copy_all(false);
+        s->step = step0;
+        if (e == hipSuccess) e = run_steps(s, 5);  // warm-up: instruction caches, clocks
+        if (e == hipSuccess) e = hipEventRecord(a, s->stream);
+        if (e == hipSuccess) e = run_steps(s, steps_per_trial);
+        if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        const double us = 1e3 * ms / steps_per_trial;
+        if (trials && nt < max_trials) trials[nt] = ldpm_tune_trial{s->launch, us};
+        nt++;
+        if (us < best_t) {
+            best_t = us;
+            best_l = s->launch;
+        }
+    }
+    // restore the state, keep the winner
+    if (e == hipSuccess) e = copy_all(false);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    s->step = step0;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (s->dev_alloc) s->dev_free(snap, s->alloc_ctx);
+    else (void)hipFree(snap);
+    if (e != hipSuccess) {
+        s->launch = keep;
+        return fail(LDPM_ERR_DEVICE, "autotune failed: %s", hipGetErrorString(e));
+    }
+    int32_t flag[2] = {0, 0};
+    HIP_TRY(hipMemcpy(flag, s->flag, 8, hipMemcpyDeviceToHost));
+    if (flag[1]) return fail(LDPM_ERR_DEVICE, "autotune: a persistent grid barrier timed out");
+    if (flag[0]) {  // a trial went non-finite: the restored state is clean, clear the flag
+        HIP_TRY(hipMemset(s->flag, 0, 4));
+    }
+    s->launch = best_l;
+    g_tune_cache.push_back(TuneEntry{key, best_l, best_t});
+    if (best) *best = best_l;
+    if (best_us) *best_us = best_t;
+    if (n_trials) *n_trials = nt;
     return LDPM_OK;
 }
 

@@ -21,7 +21,8 @@ PREC = {"fp64": 0, "mixed": 1}
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_DEVICE", 4: "ERR_UNSTABLE", 5: "ERR_STATE"}
 
 EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "ldpm_read_state", "ldpm_energy",
-           "ldpm_reaction", "ldpm_get_info", "ldpm_set_launch", "ldpm_get_launch", "ldpm_free",
+           "ldpm_reaction", "ldpm_get_info", "ldpm_set_launch", "ldpm_get_launch", "ldpm_autotune",
+           "ldpm_free",
            "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
@@ -79,7 +80,11 @@ class Info(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("tets_per_block", C.c_int32), ("particle_threads", C.c_int32),
-                ("xcd_remap", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("persistent", C.c_int32)]
+
+
+class TuneTrial(C.Structure):
+    _fields_ = [("launch", Launch), ("us_per_step", C.c_double)]
 
 
 class LdpmError(RuntimeError):
@@ -112,6 +117,8 @@ def lib():
         L.ldpm_get_info.argtypes = [C.c_void_p, C.POINTER(Info)]
         L.ldpm_set_launch.argtypes = [C.c_void_p, C.POINTER(Launch)]
         L.ldpm_get_launch.argtypes = [C.c_void_p, C.POINTER(Launch)]
+        L.ldpm_autotune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Launch), _dp,
+                                    C.POINTER(TuneTrial), C.c_int32, C.POINTER(C.c_int32)]
         L.ldpm_free.argtypes = [C.c_void_p]
         L.ldpm_free.restype = None
         L.ldpm_last_error.restype = C.c_char_p
@@ -341,15 +348,31 @@ class System:
         _check(lib().ldpm_get_info(self.h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in Info._fields_}
 
-    def set_launch(self, tets_per_block=16, particle_threads=256, xcd_remap=1):
-        c = Launch(tets_per_block, particle_threads, xcd_remap)
+    def set_launch(self, tets_per_block=16, particle_threads=256, xcd_remap=1, persistent=0):
+        c = Launch(tets_per_block, particle_threads, xcd_remap, persistent)
         _check(lib().ldpm_set_launch(self.h, C.byref(c)))
 
     def get_launch(self):
         c = Launch()
         _check(lib().ldpm_get_launch(self.h, C.byref(c)))
         return dict(tets_per_block=c.tets_per_block, particle_threads=c.particle_threads,
-                    xcd_remap=c.xcd_remap)
+                    xcd_remap=c.xcd_remap, persistent=c.persistent)
+
+    def autotune(self, steps_per_trial=100):
+        """Time every launch shape on this system, keep the fastest.  Returns
+        (best launch dict, us per step, list of (launch dict, us) trials)."""
+        best = Launch()
+        us = C.c_double()
+        cap = 64
+        arr = (TuneTrial * cap)()
+        nt = C.c_int32()
+        _check(lib().ldpm_autotune(self.h, int(steps_per_trial), C.byref(best), C.byref(us),
+                                   arr, cap, C.byref(nt)))
+        as_dict = lambda l: dict(tets_per_block=l.tets_per_block,
+                                 particle_threads=l.particle_threads, xcd_remap=l.xcd_remap,
+                                 persistent=l.persistent)
+        trials = [(as_dict(arr[i].launch), arr[i].us_per_step) for i in range(min(nt.value, cap))]
+        return as_dict(best), us.value, trials
 
     def close(self):
         if getattr(self, "h", None):

@@ -836,3 +836,31 @@ def few_particle(n=12, seed=3, mat=None):
     x = g * 7.0 + rng.uniform(-1.2, 1.2, g.shape)
     diam = rng.uniform(3.0, 4.5, n)
     return system_from_points(x, diam, mat=mat, name=f"few{n}_s{seed}")
+
+
+def _sliding_one(args):
+    edge, seed, d0, da, rate = args
+    return sliding_compression_cube(edge, d0=d0, da=da, seed=seed, rate=rate)
+
+
+def batch_sliding_compression(n=64, seed=0, edge_range=(50.0, 100.0), d0=4.0, da=8.0,
+                              rate=2.5e-2, workers=None):
+    """n seeded realisations of unconfined compression with sliding platens,
+    cube edges drawn uniformly from edge_range, concatenated into one batched
+    system advancing with the smallest stable step of the set."""
+    import concurrent.futures as cf
+    import os
+    rng = np.random.default_rng(seed)
+    edges = rng.uniform(edge_range[0], edge_range[1], n)
+    jobs = [(float(e), int(seed * 1000 + i), d0, da, rate) for i, e in enumerate(edges)]
+    workers = workers or min(16, os.cpu_count() or 1, n)
+    if workers > 1:
+        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+            specs = list(ex.map(_sliding_one, jobs))
+    else:
+        specs = [_sliding_one(j) for j in jobs]
+    out = concat_specimens(specs)
+    out["name"] = f"batch_sliding{n}_s{seed}"
+    out["meta"].update(edges=edges.tolist(), specimen_F=[s["meta"]["F"] for s in specs],
+                       load_progs=[int(s["meta"]["load_prog"]) for s in specs], rate=rate)
+    return out

@@ -251,3 +251,54 @@ def test_mixed_precision_accuracy_tension():
     assert peak_err <= 1e-2
     assert eg["err"] <= 1e-3
     assert abs(eg["W_int"] - eo["W_int"]) <= 1e-2 * abs(eo["W_int"])
+
+
+@pytest.mark.parametrize("tb", [16, 32])
+def test_persistent_launch_is_bitwise_equal(tb):
+    """n steps in persistent cooperative launches (with a chunk boundary at
+    1024 steps) give the same bits as two kernels per step."""
+    s = tension_small()
+    ref = gpu(s).step(1100).read_state()
+    g = gpu(s)
+    g.set_launch(tets_per_block=tb, persistent=1)
+    st = g.step(1100).read_state()
+    g.sync()
+    for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
+        assert np.array_equal(st[k], ref[k]), k
+
+
+def test_autotune_keeps_the_trajectory():
+    """The autotuner runs trials on the live system and restores its state:
+    the continued trajectory is bitwise the one without tuning."""
+    s = tension_small()
+    ref = gpu(s).step(300).read_state()
+    g = gpu(s).step(100)
+    best, us, trials = g.autotune(steps_per_trial=20)
+    assert len(trials) == 27 and us > 0
+    assert best in [t[0] for t in trials]
+    st = g.step(200).read_state()
+    for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
+        assert np.array_equal(st[k], ref[k]), k
+    assert g.get_launch() == best
+
+
+def test_batched_uneven_specimens_against_oracle():
+    """Three specimens of uneven size in one batched system: per-specimen
+    energies and reactions from the GPU against the oracle run of each."""
+    specs = [S.sliding_compression_cube(e, d0=4.0, da=8.0, seed=10 + i, rate=1.0, ramp=2e-4)
+             for i, e in enumerate((20.0, 31.0, 25.0))]
+    dt = min(x["dt"] for x in specs)
+    batch = S.concat_specimens(specs, dt=dt)
+    g = gpu(batch)
+    g.set_launch(tets_per_block=32)
+    g.step(400)
+    for i, sp in enumerate(specs):
+        sp = dict(sp)
+        sp["dt"] = dt
+        o = O.Oracle(sp).step(400)
+        eo, eg = o.energies(), g.energy(i)
+        for k in ("W_int", "W_ext", "W_kin"):
+            assert abs(eg[k] - eo[k]) <= TOL_TRAJ * abs(eo[k]), (i, k, eg[k], eo[k])
+        ro = o.reaction_sum(sp["meta"]["load_prog"])
+        rg = g.reaction(i)          # specimen i's single program is batched id i
+        assert abs(rg - ro) <= TOL_TRAJ * abs(ro), (i, rg, ro)
