@@ -234,6 +234,34 @@ ldpm_status ldpm_autotune(ldpm_system *s, int32_t steps_per_trial, ldpm_launch *
                           double *best_us, ldpm_tune_trial *trials, int32_t max_trials,
                           int32_t *n_trials);
 
+/* ---- Facet-law surrogate: a small MLP trained on the GPU ------------------
+ * Network 9 -> 64 -> 64 -> 64 -> 3 with tanh, parameters as one flat FP32
+ * vector of ldpm_mlp_num_params() = 9155 values, weights stored [out][in]:
+ *   W1[64][9] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3].
+ * Forward and backward run on BF16 matrix-core tiles with FP32
+ * accumulation; the trainer keeps FP32 master weights and Adam moments.
+ * Loss: mean over the batch of sum_j (y_j - target_j)^2.
+ * For callers that bring their own (normalised) training data; the solver
+ * uses the trained parameters through ldpm_set_surrogate.                 */
+typedef struct ldpm_mlp ldpm_mlp;
+int32_t ldpm_mlp_num_params(void);
+/* init: host FP32 parameters (copied).  stream: hipStream_t or NULL. */
+ldpm_status ldpm_mlp_create(const float *init, void *stream, ldpm_mlp **out);
+/* Training data: host x[n][9], y[n][3] (copied; replaces previous data). */
+ldpm_status ldpm_mlp_set_data(ldpm_mlp *m, const float *x, const float *y, int64_t n);
+/* Gradient (host grad[9155]) and loss of the current parameters over the
+ * batch of samples offset .. offset+batch-1 (indices modulo n; batch is
+ * rounded up to a multiple of 64).  No update.                              */
+ldpm_status ldpm_mlp_grad(ldpm_mlp *m, int32_t batch, int64_t offset, float *grad, float *loss);
+/* steps Adam updates over consecutive batches of the data (wrapping);
+ * *last_loss receives the loss of the last batch.                          */
+ldpm_status ldpm_mlp_train(ldpm_mlp *m, int64_t steps, int32_t batch, float lr, float *last_loss);
+/* Forward pass of host x[n][9] into host y[n][3] (the surrogate's path). */
+ldpm_status ldpm_mlp_forward(ldpm_mlp *m, const float *x, int64_t n, float *y);
+/* Current FP32 master parameters into host params[9155]. */
+ldpm_status ldpm_mlp_get_params(ldpm_mlp *m, float *params);
+void ldpm_mlp_free(ldpm_mlp *m);
+
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);
 

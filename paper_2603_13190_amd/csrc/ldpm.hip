@@ -58,6 +58,17 @@ static ldpm_status fail(ldpm_status st, const char* fmt, ...)
     return st;
 }
 
+ldpm_status ldpm_fail(ldpm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
 #define HIP_TRY(expr)                                                                     \
     do {                                                                                  \
         hipError_t _e = (expr);                                                           \

@@ -22,7 +22,9 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_DEVICE", 4: "ERR_UNSTA
 
 EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "ldpm_read_state", "ldpm_energy",
            "ldpm_reaction", "ldpm_get_info", "ldpm_set_launch", "ldpm_get_launch", "ldpm_autotune",
-           "ldpm_free",
+           "ldpm_free", "ldpm_mlp_num_params", "ldpm_mlp_create", "ldpm_mlp_set_data",
+           "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
+           "ldpm_mlp_free",
            "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
@@ -33,6 +35,7 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 _lp = C.POINTER(C.c_int64)
 _up = C.POINTER(C.c_uint8)
+_fp = C.POINTER(C.c_float)
 
 
 class Material(C.Structure):
@@ -119,11 +122,20 @@ def lib():
         L.ldpm_get_launch.argtypes = [C.c_void_p, C.POINTER(Launch)]
         L.ldpm_autotune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Launch), _dp,
                                     C.POINTER(TuneTrial), C.c_int32, C.POINTER(C.c_int32)]
+        L.ldpm_mlp_num_params.restype = C.c_int32
+        L.ldpm_mlp_create.argtypes = [_fp, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.ldpm_mlp_set_data.argtypes = [C.c_void_p, _fp, _fp, C.c_int64]
+        L.ldpm_mlp_grad.argtypes = [C.c_void_p, C.c_int32, C.c_int64, _fp, _fp]
+        L.ldpm_mlp_train.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_float, _fp]
+        L.ldpm_mlp_forward.argtypes = [C.c_void_p, _fp, C.c_int64, _fp]
+        L.ldpm_mlp_get_params.argtypes = [C.c_void_p, _fp]
+        L.ldpm_mlp_free.argtypes = [C.c_void_p]
+        L.ldpm_mlp_free.restype = None
         L.ldpm_free.argtypes = [C.c_void_p]
         L.ldpm_free.restype = None
         L.ldpm_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("ldpm_free", "ldpm_last_error"):
+            if name not in ("ldpm_free", "ldpm_last_error", "ldpm_mlp_free", "ldpm_mlp_num_params"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -377,6 +389,62 @@ class System:
     def close(self):
         if getattr(self, "h", None):
             lib().ldpm_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Mlp:
+    """GPU trainer of the facet-law surrogate (ldpm_mlp_* of the C-ABI)."""
+
+    def __init__(self, params, stream=None):
+        import torch  # noqa: F401  (HIP runtime and stream provider)
+        L = lib()
+        self.n_params = int(L.ldpm_mlp_num_params())
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        h = C.c_void_p()
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(L.ldpm_mlp_create(p.ctypes.data_as(_fp), st, C.byref(h)))
+        self.h = h
+
+    def set_data(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        assert x.shape[1] == 9 and y.shape[1] == 3 and x.shape[0] == y.shape[0]
+        _check(lib().ldpm_mlp_set_data(self.h, x.ctypes.data_as(_fp), y.ctypes.data_as(_fp),
+                                       int(x.shape[0])))
+        self.n = x.shape[0]
+
+    def grad(self, batch, offset=0):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().ldpm_mlp_grad(self.h, int(batch), int(offset), g.ctypes.data_as(_fp), C.byref(loss)))
+        return float(loss.value), g
+
+    def train(self, steps, batch=4096, lr=1e-3):
+        loss = C.c_float()
+        _check(lib().ldpm_mlp_train(self.h, int(steps), int(batch), float(lr), C.byref(loss)))
+        return float(loss.value)
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros((x.shape[0], 3), dtype=np.float32)
+        _check(lib().ldpm_mlp_forward(self.h, x.ctypes.data_as(_fp), int(x.shape[0]), y.ctypes.data_as(_fp)))
+        return y
+
+    def params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().ldpm_mlp_get_params(self.h, p.ctypes.data_as(_fp)))
+        return p
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ldpm_mlp_free(self.h)
             self.h = None
 
     def __del__(self):
