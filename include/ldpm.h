@@ -262,6 +262,53 @@ ldpm_status ldpm_mlp_forward(ldpm_mlp *m, const float *x, int64_t n, float *y);
 ldpm_status ldpm_mlp_get_params(ldpm_mlp *m, float *params);
 void ldpm_mlp_free(ldpm_mlp *m);
 
+/* ---- Surrogate of the facet law inside the step ----------------------------
+ * With a surrogate installed (precision MIXED, law 1), every facet that is
+ * inside the network's envelope and has not been handed back is updated by
+ * t = t_old + E de + y_scale * MLP(x_hat) instead of the exact law, where
+ * x are the facet's features in the frame aligned with its trial shear
+ * traction t_old,T + alpha E0 de_T:
+ *   x = [de_N, de_par, de_perp, e_N, e_par, e_perp, t_N, t_par, t_perp]_old,
+ * x_hat = (x - x_mean) * x_scale, and the output is the traction residual
+ * over the elastic predictor in the same frame.  A facet is handed back to
+ * the exact FP32 law for good (sticky flag) when
+ *   - a feature leaves [box_lo, box_hi] (the trained range), or
+ *   - tension: its effective strain reaches kappa_t e0(omega), or its e_max
+ *     reaches kappa_t sigma_t / E0 (pre-peak envelope), or
+ *   - compression: -e_DV reaches kappa_c e_c0 or -t_N reaches kappa_c sigma_c0
+ *     (onset of pore collapse), or
+ *   - the damage D = 1 - t / (E0 e) of the surrogate's traction exceeds
+ *     damage_max.
+ * NULL removes the surrogate.  (For callers comparing a learned law with the
+ * exact one; the exact law stays the reference.)                           */
+typedef struct {
+    const float *params;                    /* [ldpm_mlp_num_params()] FP32, copied */
+    float x_mean[9], x_scale[9], y_scale[3];
+    float box_lo[9], box_hi[9];
+    float kappa_t, kappa_c, damage_max;
+} ldpm_surrogate;
+ldpm_status ldpm_set_surrogate(ldpm_system *s, const ldpm_surrogate *sg);
+/* Number of facets handed back to the exact law so far. */
+ldpm_status ldpm_surrogate_count(ldpm_system *s, int64_t *n_exact);
+
+/* ---- Capture of surrogate training samples from the FP64 exact law -------
+ * While a capture is active (precision FP64, law 1), every step n with
+ * n % step_stride == 0 records, for the facets f with
+ * f % facet_stride == facet_offset that are inside the envelope (same
+ * criteria as above with kappa_t, kappa_c, damage_max), one row of 16 floats:
+ * x[9] (features as above), the exact residual t - (t_old + E de) in the
+ * aligned frame [3], and the key n * 2^32 + f as an int64 in floats 12-13.
+ * Rows land in arrival order; sort by key for a reproducible order.        */
+typedef struct {
+    int64_t capacity;         /* rows */
+    int32_t facet_stride, facet_offset, step_stride;
+    float kappa_t, kappa_c, damage_max;
+} ldpm_capture_opts;
+ldpm_status ldpm_capture_begin(ldpm_system *s, const ldpm_capture_opts *opts);
+/* Ends the capture; *n_rows = rows offered (may exceed the capacity);
+ * copies min(n_rows, capacity, max_rows) rows into host rows[][16].      */
+ldpm_status ldpm_capture_end(ldpm_system *s, float *rows, int64_t max_rows, int64_t *n_rows);
+
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);
 

@@ -31,6 +31,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -39,6 +40,7 @@
 
 #include "../../include/ldpm.h"
 #include "law.hpp"
+#include "mlp.hpp"
 
 using namespace ldpm;
 
@@ -127,6 +129,29 @@ __device__ __forceinline__ double prog_at(const ProgArgs& pr, int64_t p, double 
     return pr.v[b - 1];
 }
 
+// Facet-kernel modes: plain step, plain step that also records surrogate
+// training samples, step with the MLP surrogate in place of the law.
+enum { MODE_PLAIN = 0, MODE_CAPTURE = 1, MODE_SURROGATE = 2 };
+
+struct GateArgs {
+    float kappa_t, kappa_c, damage_max;
+};
+
+struct SurrogateArgs {
+    const float* __restrict__ params;  // [MLP_NPARAM] FP32
+    uint8_t* __restrict__ flag;        // [F] sticky: 1 = handed back to the exact law
+    float xmean[MLP_IN], xscale[MLP_IN], yscale[MLP_OUT], lo[MLP_IN], hi[MLP_IN];
+    GateArgs gate;
+};
+
+struct CaptureArgs {
+    float* __restrict__ rows;          // [cap][16]: x[9], residual[3], key (int64 bits)
+    unsigned* __restrict__ count;
+    int64_t cap;
+    int32_t fstride, foff, sstride;
+    GateArgs gate;
+};
+
 struct ParticleArgs {
     double* __restrict__ q;           // [6][N]
     double* __restrict__ v;           // [6][N]
@@ -159,13 +184,83 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap)
     return x * qn + (x < r ? x : r) + k;
 }
 
+// Is the facet inside the surrogate's envelope (the pre-peak elastic and
+// frictional regime the network is trained on)?  Tension: the effective
+// strain and e_max stay below kappa_t of the elastic limit e0(omega) (and of
+// sigma_t/E0 for e_max, whatever the angle); compression: -e_DV and -t_N stay
+// below kappa_c of the onset of pore collapse (e_c0, sigma_c0).
+template <typename R>
+__device__ __forceinline__ bool in_envelope(const MatDev<R>& p, const R e[3], R eV, const R told[3], R emax,
+                                            const GateArgs& g)
+{
+    const R emax_lim = (R)g.kappa_t * p.sigma_t * p.inv_E0;
+    if (emax >= emax_lim) return false;
+    if (e[0] > R(0)) {
+        R sN, sT2, seff, seff2;
+        int ex;
+        scaled_norm(e[0], e[1], e[2], p.alpha, sN, sT2, seff, seff2, ex);
+        const R eff = d_ldexp(seff, ex);
+        const R inv = R(1) / seff;
+        const R sn = sN * inv, cs2 = p.alpha * sT2 * (inv * inv);
+        const R sigma0 = R(2) * p.sigma_t / (sn + d_sqrt(sn * sn + p.c4 * cs2));
+        return eff < (R)g.kappa_t * sigma0 * p.inv_E0;
+    }
+    const R eD = e[0] - eV;
+    const R eDV = eV + p.beta * eD;
+    return (-eDV < (R)g.kappa_c * p.ec0) && (-told[0] < (R)g.kappa_c * p.sigma_c0);
+}
+
+// damage D = 1 - t/(E0 e) of a tensile facet (0 in compression)
+template <typename R>
+__device__ __forceinline__ float facet_damage(const MatDev<R>& p, const R e[3], const R t[3])
+{
+    if (!(e[0] > R(0))) return 0.f;
+    R sN, sT2, seff, seff2;
+    int ex;
+    scaled_norm(e[0], e[1], e[2], p.alpha, sN, sT2, seff, seff2, ex);
+    const R eff = d_ldexp(seff, ex);
+    const R teff = d_sqrt(t[0] * t[0] + (t[1] * t[1] + t[2] * t[2]) * p.inv_alpha);
+    return (float)(R(1) - teff / (p.E0 * eff));
+}
+
+// surrogate features (aligned with the trial shear traction) of a facet
+template <typename R>
+__device__ __forceinline__ AlignedFrame surrogate_features(const MatDev<R>& p, const R e[3], const R de[3],
+                                                           const R told[3], float x[MLP_IN])
+{
+    const AlignedFrame fr =
+        shear_frame((float)(told[1] + p.aE0 * de[1]), (float)(told[2] + p.aE0 * de[2]));
+    x[0] = (float)de[0];
+    to_frame(fr, (float)de[1], (float)de[2], x[1], x[2]);
+    x[3] = (float)(e[0] - de[0]);
+    to_frame(fr, (float)(e[1] - de[1]), (float)(e[2] - de[2]), x[4], x[5]);
+    x[6] = (float)told[0];
+    to_frame(fr, (float)told[1], (float)told[2], x[7], x[8]);
+    return fr;
+}
+
+// LDS of the surrogate: weights of the block plus one activation tile per wave
+template <int NW>
+struct MlpSmem {
+    MlpBf16 W;
+    __bf16 buf[NW][64 * PA];
+    float out[NW][64 * 4];
+};
+template <int NW>
+__device__ __forceinline__ MlpSmem<NW>& mlp_smem()
+{
+    __shared__ MlpSmem<NW> sm;
+    return sm;
+}
+
 // One tile of TB tetrahedra (block-wide: every thread of a 12 TB block calls
 // it together).  do_prog: this block also evaluates the time programs.
-template <typename R, int LAW, int TB>
+template <typename R, int LAW, int TB, int MODE>
 __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const NodeArgs& na, const FacetArgs<R>& fa,
                                            const MatDev<R>& mat, const int32_t* __restrict__ pos,
                                            R* __restrict__ contrib, double* __restrict__ wint,
-                                           const ProgArgs& pr, int64_t step, double dt)
+                                           const ProgArgs& pr, int64_t step, double dt,
+                                           const SurrogateArgs& sg, const CaptureArgs& cp)
 {
     const int first = step == 0;
     constexpr int NS = 4 * TB;   // node slots per block
@@ -182,6 +277,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
 
     const int tid = threadIdx.x;
     const int64_t tet0 = blk * TB;
+    if constexpr (MODE == MODE_SURROGATE) mlp_load_bf16(sg.params, mlp_smem<NF / 64>().W, tid, NF);
     const int64_t T = na.T, N = na.N;
 
     // ---- facet data for lane tid, issued before the node gather so that
@@ -265,19 +361,25 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     }
     __syncthreads();
 
-    // ---- C: one lane per facet ----
-    if (tid < NF) {
+    // ---- C: one lane per facet (blockDim == NF: every lane takes part) ----
+    {
         const int tl = ftl;
         double wk = 0.0;
         uint8_t code = 0xff;
+        const int64_t F = fa.F;
+        R e[3] = {R(0), R(0), R(0)}, de[3] = {R(0), R(0), R(0)}, eV = R(0);
+        R l0 = 0, l1 = 0, l2 = 0, cJ0 = 0, cJ1 = 0, cJ2 = 0;
+        const R told[3] = {tv[0], tv[1], tv[2]};
         if (fvalid) {
-            const int64_t F = fa.F;
             const int aI = (rc >> 28) & 3, aJ = (rc >> 30) & 3;
             code = (uint8_t)(aI | (aJ << 2));
             const int sI = aI * TB + tl, sJ = aJ * TB + tl;
-            const R l0 = n1 * m2 - n2 * m1, l1 = n2 * m0 - n0 * m2, l2 = n0 * m1 - n1 * m0;
-            const R cJ0 = cI0 - len * n0, cJ1 = cI1 - len * n1, cJ2 = cI2 - len * n2;
-            const R told0 = tv[0], told1 = tv[1], told2 = tv[2];
+            l0 = n1 * m2 - n2 * m1;
+            l1 = n2 * m0 - n0 * m2;
+            l2 = n0 * m1 - n1 * m0;
+            cJ0 = cI0 - len * n0;
+            cJ1 = cI1 - len * n1;
+            cJ2 = cI2 - len * n2;
             // displacement jump [[u]] = u_J + th_J x c^J - u_I - th_I x c^I
             // (translation difference in FP64, rotation terms in R)
             R d[3], dv[3];
@@ -300,7 +402,6 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                 dv[2] = dv2 + (wJ0 * cJ1 - wJ1 * cJ0) - (wI0 * cI1 - wI1 * cI0);
             }
             const R il = R(1) / len;
-            R e[3], de[3];
             e[0] = (n0 * d[0] + n1 * d[1] + n2 * d[2]) * il;
             e[1] = (m0 * d[0] + m1 * d[1] + m2 * d[2]) * il;
             e[2] = (l0 * d[0] + l1 * d[1] + l2 * d[2]) * il;
@@ -314,15 +415,101 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                 de[1] = (m0 * dv[0] + m1 * dv[1] + m2 * dv[2]) * sc;
                 de[2] = (l0 * dv[0] + l1 * dv[1] + l2 * dv[2]) * sc;
             }
-            const R eV = (R)((s_ev[tl] + s_ev[TB + tl] + s_ev[2 * TB + tl] + s_ev[3 * TB + tl]) / 3.0);
-            facet_law<R, LAW>(mat, len, e, de, eV, tv, emx);
+            eV = (R)((s_ev[tl] + s_ev[TB + tl] + s_ev[2 * TB + tl] + s_ev[3 * TB + tl]) / 3.0);
+        }
+        bool exact = fvalid;
+        if constexpr (MODE == MODE_SURROGATE) {
+            // gate: in-envelope facets not yet handed back go through the MLP
+            uint8_t fl = 1;
+            float x[MLP_IN];
+            AlignedFrame fr{1.f, 0.f};
+            if (fvalid) {
+                fl = sg.flag[f];
+                fr = surrogate_features(mat, e, de, told, x);
+                if (!fl) {
+                    bool ok = in_envelope(mat, e, eV, told, emx, sg.gate);
+#pragma unroll
+                    for (int k = 0; k < MLP_IN; k++) ok = ok && x[k] >= sg.lo[k] && x[k] <= sg.hi[k];
+                    if (!ok) fl = 1;
+                }
+            }
+            const bool use_nn = fvalid && !fl;
+            auto& sm = mlp_smem<NF / 64>();
+            const int w = tid >> 6, lane = tid & 63;
+            if (__any(use_nn)) {  // wave-uniform: the whole wave runs the tiles
+                __bf16* buf = sm.buf[w];
+#pragma unroll
+                for (int k = 0; k < K1; k++)
+                    buf[lane * PA + k] =
+                        to_bf16((use_nn && k < MLP_IN) ? (x[k] - sg.xmean[k]) * sg.xscale[k] : 0.f);
+                __builtin_amdgcn_wave_barrier();
+                mlp_forward_wave(sm.W, buf, sm.out[w]);
+                if (use_nn) {
+                    // traction = elastic predictor + scaled residual, back in (n, m, l)
+                    const float r0 = sm.out[w][lane * 4 + 0] * sg.yscale[0];
+                    const float r1 = sm.out[w][lane * 4 + 1] * sg.yscale[1];
+                    const float r2 = sm.out[w][lane * 4 + 2] * sg.yscale[2];
+                    float rM, rL;
+                    from_frame(fr, r1, r2, rM, rL);
+                    R tn[3];
+                    tn[0] = told[0] + mat.E0 * de[0] + (R)r0;
+                    tn[1] = told[1] + mat.aE0 * de[1] + (R)rM;
+                    tn[2] = told[2] + mat.aE0 * de[2] + (R)rL;
+                    if (facet_damage(mat, e, tn) > sg.gate.damage_max) {
+                        fl = 1;  // leaves the envelope: exact law from now on
+                    } else {
+                        tv[0] = tn[0];
+                        tv[1] = tn[1];
+                        tv[2] = tn[2];
+                        if (e[0] > R(0)) {  // keep e_max for a later hand-back
+                            R sN, sT2, seff, seff2;
+                            int ex;
+                            scaled_norm(e[0], e[1], e[2], mat.alpha, sN, sT2, seff, seff2, ex);
+                            const R eff = d_ldexp(seff, ex);
+                            emx = emx > eff ? emx : eff;
+                        }
+                        exact = false;
+                    }
+                }
+            }
+            if (fvalid && fl && !sg.flag[f]) sg.flag[f] = 1;
+        }
+        if (exact) facet_law<R, LAW>(mat, len, e, de, eV, tv, emx);
+        if constexpr (MODE == MODE_CAPTURE) {
+            if (fvalid && (f % cp.fstride) == cp.foff && (step % cp.sstride) == 0 &&
+                in_envelope(mat, e, eV, told, (R)fa.hemax[f], cp.gate) &&
+                facet_damage(mat, e, tv) <= cp.gate.damage_max) {
+                float x[MLP_IN];
+                const AlignedFrame fr = surrogate_features(mat, e, de, told, x);
+                const R rN = tv[0] - (told[0] + mat.E0 * de[0]);
+                const R rM = tv[1] - (told[1] + mat.aE0 * de[1]);
+                const R rL = tv[2] - (told[2] + mat.aE0 * de[2]);
+                float rp, rq;
+                to_frame(fr, (float)rM, (float)rL, rp, rq);
+                const unsigned slot = atomicAdd(cp.count, 1u);
+                if (slot < (unsigned)cp.cap) {
+                    float* row = cp.rows + (int64_t)slot * 16;
+#pragma unroll
+                    for (int k = 0; k < MLP_IN; k++) row[k] = x[k];
+                    row[9] = (float)rN;
+                    row[10] = rp;
+                    row[11] = rq;
+                    const int64_t key = step * 4294967296ll + f;
+                    row[12] = __int_as_float((int)(key & 0xffffffff));
+                    row[13] = __int_as_float((int)(key >> 32));
+                    row[14] = 0.f;
+                    row[15] = 0.f;
+                }
+            }
+        }
+        if (fvalid) {
             fa.ht[f] = tv[0];
             fa.ht[F + f] = tv[1];
             fa.ht[2 * F + f] = tv[2];
             if (LAW != 0) fa.hemax[f] = emx;
             // internal work A l (t_old + t)/2 . de
             wk = (double)(A * len * R(0.5) *
-                          ((told0 + tv[0]) * de[0] + (told1 + tv[1]) * de[1] + (told2 + tv[2]) * de[2]));
+                          ((told[0] + tv[0]) * de[0] + (told[1] + tv[1]) * de[1] + (told[2] + tv[2]) * de[2]));
             // facet force A P t and its moments about I and J
             const R F0 = A * (tv[0] * n0 + tv[1] * m0 + tv[2] * l0);
             const R F1 = A * (tv[0] * n1 + tv[1] * m1 + tv[2] * l1);
@@ -380,14 +567,15 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     }
 }
 
-template <typename R, int LAW, int TB>
+template <typename R, int LAW, int TB, int MODE>
 __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
                                                    const int32_t* __restrict__ pos,
                                                    R* __restrict__ contrib, double* __restrict__ wint,
-                                                   ProgArgs pr, int64_t step, double dt, int remap)
+                                                   ProgArgs pr, int64_t step, double dt, int remap,
+                                                   SurrogateArgs sg, CaptureArgs cp)
 {
-    facet_tile<R, LAW, TB>(xcd_block(blockIdx.x, gridDim.x, remap), blockIdx.x == 0, na, fa, mat, pos, contrib,
-                           wint, pr, step, dt);
+    facet_tile<R, LAW, TB, MODE>(xcd_block(blockIdx.x, gridDim.x, remap), blockIdx.x == 0, na, fa, mat, pos,
+                                 contrib, wint, pr, step, dt, sg, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -528,7 +716,8 @@ template <typename R, int LAW, int TB>
 __global__ __launch_bounds__(12 * TB) void k_persist(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
                                                      const int32_t* __restrict__ pos, R* __restrict__ contrib,
                                                      double* __restrict__ wint, ProgArgs pr, ParticleArgs pa,
-                                                     GridSync gs, int64_t step0, int64_t nsteps, double dt)
+                                                     GridSync gs, int64_t step0, int64_t nsteps, double dt,
+                                                     SurrogateArgs sg, CaptureArgs cp)
 {
     const int64_t nb = (na.T + TB - 1) / TB;
     const unsigned G = gridDim.x;
@@ -536,7 +725,7 @@ __global__ __launch_bounds__(12 * TB) void k_persist(NodeArgs na, FacetArgs<R> f
     for (int64_t i = 0; i < nsteps; i++) {
         const int64_t n = step0 + i;
         for (int64_t blk = blockIdx.x; blk < nb; blk += G)
-            facet_tile<R, LAW, TB>(blk, blk == 0, na, fa, mat, pos, contrib, wint, pr, n, dt);
+            facet_tile<R, LAW, TB, MODE_PLAIN>(blk, blk == 0, na, fa, mat, pos, contrib, wint, pr, n, dt, sg, cp);
         if (!grid_barrier(gs, G)) return;
         for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < lanes; gt += (int64_t)G * blockDim.x)
             particle_group<R>(gt, pa, contrib, n, dt);
@@ -625,6 +814,12 @@ struct ldpm_system {
     int64_t n_prog_pts = 0, n_prog = 0;
     MatDev<double> matd;
     MatDev<float> matf;
+    // surrogate (mixed precision, full law) and training-sample capture (FP64)
+    bool sg_on = false, cp_on = false;
+    SurrogateArgs sg{};
+    CaptureArgs cp{};
+    void* sg_mem = nullptr;  // params + flags
+    void* cp_mem = nullptr;  // rows + counter
 };
 
 namespace {
@@ -714,8 +909,8 @@ size_t rbytes(int prec) { return prec == LDPM_PREC_MIXED ? 4 : 8; }
 // Kernel launches.  With events (ev0, ev1) the launch is made with
 // hipExtLaunchKernelGGL, whose start/stop events are timestamped by the
 // dispatch itself (the kernel's own duration, as a profiler reports it).
-template <typename R, int LAW, int TB>
-static void launch_facet_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
+template <typename R, int LAW, int TB, int MODE>
+static void launch_facet_m(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
     NodeArgs na{s->tet, s->x0, s->q, s->v, s->N, s->T};
     FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->en, (const R*)s->em,
@@ -724,12 +919,30 @@ static void launch_facet_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
     const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
     const int64_t nb = (s->T + TB - 1) / TB;
     if (ev0)
-        hipExtLaunchKernelGGL((k_facet<R, LAW, TB>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, ev0, ev1, 0,
-                              na, fa, mat, (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt,
-                              s->launch.xcd_remap);
+        hipExtLaunchKernelGGL((k_facet<R, LAW, TB, MODE>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, ev0, ev1,
+                              0, na, fa, mat, (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt,
+                              s->launch.xcd_remap, s->sg, s->cp);
     else
-        hipLaunchKernelGGL((k_facet<R, LAW, TB>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
-                           (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt, s->launch.xcd_remap);
+        hipLaunchKernelGGL((k_facet<R, LAW, TB, MODE>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
+                           (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt, s->launch.xcd_remap,
+                           s->sg, s->cp);
+}
+
+template <typename R, int LAW, int TB>
+static void launch_facet_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if constexpr (LAW == 1 && std::is_same<R, double>::value) {
+        if (s->cp_on) return launch_facet_m<R, LAW, TB, MODE_CAPTURE>(s, ev0, ev1);
+    }
+    if constexpr (LAW == 1 && std::is_same<R, float>::value && TB <= 32) {
+        if (s->sg_on) return launch_facet_m<R, LAW, TB, MODE_SURROGATE>(s, ev0, ev1);
+    }
+    if constexpr (LAW == 1 && std::is_same<R, float>::value && TB == 64) {
+        // the surrogate's weights and activation tiles do not fit next to a
+        // 64-tet tile in LDS: it runs with 32-tet tiles
+        if (s->sg_on) return launch_facet_m<R, LAW, 32, MODE_SURROGATE>(s, ev0, ev1);
+    }
+    launch_facet_m<R, LAW, TB, MODE_PLAIN>(s, ev0, ev1);
 }
 
 template <typename R, int LAW>
@@ -805,7 +1018,9 @@ static hipError_t launch_persist_t(ldpm_system* s, int64_t nsteps)
     for (int64_t done = 0; done < nsteps;) {
         int64_t k = std::min<int64_t>(PERSIST_CHUNK, nsteps - done);
         int64_t step0 = s->step;
-        void* args[] = {&na, &fa, &mat, &pos, &contrib, &wint, &pr, &pa, &gs, &step0, &k, &dt};
+        SurrogateArgs sg = s->sg;
+        CaptureArgs cp = s->cp;
+        void* args[] = {&na, &fa, &mat, &pos, &contrib, &wint, &pr, &pa, &gs, &step0, &k, &dt, &sg, &cp};
         e = hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)G), dim3(12 * TB), args, 0, s->stream);
         if (e != hipSuccess) return e;
         s->step += k;
@@ -834,7 +1049,7 @@ static hipError_t launch_persist(ldpm_system* s, int64_t n)
 // n steps in the configured launch shape
 static hipError_t run_steps(ldpm_system* s, int64_t n)
 {
-    if (s->launch.persistent) return launch_persist(s, n);
+    if (s->launch.persistent && !s->sg_on && !s->cp_on) return launch_persist(s, n);
     for (int64_t i = 0; i < n; i++) {
         launch_facet(s);
         launch_particle(s);
@@ -1453,6 +1668,105 @@ ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* 
     return LDPM_OK;
 }
 
+ldpm_status ldpm_set_surrogate(ldpm_system* s, const ldpm_surrogate* g)
+{
+    if (!s) return fail(LDPM_ERR_ARG, "null handle");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->sg_mem) (void)hipFree(s->sg_mem);
+    s->sg_mem = nullptr;
+    s->sg_on = false;
+    s->sg = SurrogateArgs{};
+    if (!g) return LDPM_OK;
+    if (s->prec != LDPM_PREC_MIXED || s->law != 1)
+        return fail(LDPM_ERR_STATE, "the surrogate replaces the FP32 facet law: needs precision MIXED and law 1");
+    if (!g->params) return fail(LDPM_ERR_ARG, "surrogate: null parameters");
+    for (int k = 0; k < MLP_NPARAM; k++)
+        if (!std::isfinite(g->params[k])) return fail(LDPM_ERR_ARG, "surrogate: non-finite parameter %d", k);
+    const size_t pbytes = ((size_t)MLP_NPARAM * 4 + 255) & ~size_t(255);
+    if (hipMalloc(&s->sg_mem, pbytes + (size_t)s->F) != hipSuccess) {
+        s->sg_mem = nullptr;
+        return fail(LDPM_ERR_ALLOC, "surrogate: allocation failed");
+    }
+    SurrogateArgs a{};
+    a.params = (const float*)s->sg_mem;
+    a.flag = (uint8_t*)((char*)s->sg_mem + pbytes);
+    for (int k = 0; k < MLP_IN; k++) {
+        a.xmean[k] = g->x_mean[k];
+        a.xscale[k] = g->x_scale[k];
+        a.lo[k] = g->box_lo[k];
+        a.hi[k] = g->box_hi[k];
+    }
+    for (int k = 0; k < MLP_OUT; k++) a.yscale[k] = g->y_scale[k];
+    a.gate = GateArgs{g->kappa_t, g->kappa_c, g->damage_max};
+    HIP_TRY(hipMemcpyAsync((void*)a.params, g->params, (size_t)MLP_NPARAM * 4, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemsetAsync(a.flag, 0, (size_t)s->F, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->sg = a;
+    s->sg_on = true;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_surrogate_count(ldpm_system* s, int64_t* n_exact)
+{
+    if (!s || !n_exact) return fail(LDPM_ERR_ARG, "null argument");
+    if (!s->sg_on) return fail(LDPM_ERR_STATE, "no surrogate installed");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::vector<uint8_t> f((size_t)s->F);
+    HIP_TRY(hipMemcpy(f.data(), s->sg.flag, (size_t)s->F, hipMemcpyDeviceToHost));
+    int64_t c = 0;
+    for (uint8_t v : f) c += v != 0;
+    *n_exact = c;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_capture_begin(ldpm_system* s, const ldpm_capture_opts* o)
+{
+    if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
+    if (s->prec != LDPM_PREC_FP64 || s->law != 1)
+        return fail(LDPM_ERR_STATE, "capture records the FP64 full law: needs precision FP64 and law 1");
+    if (o->capacity <= 0 || o->facet_stride <= 0 || o->step_stride <= 0 || o->facet_offset < 0 ||
+        o->facet_offset >= o->facet_stride)
+        return fail(LDPM_ERR_ARG, "capture: bad options");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->cp_mem) (void)hipFree(s->cp_mem);
+    s->cp_mem = nullptr;
+    const size_t rows = (size_t)o->capacity * 16 * 4;
+    if (hipMalloc(&s->cp_mem, rows + 256) != hipSuccess) {
+        s->cp_mem = nullptr;
+        return fail(LDPM_ERR_ALLOC, "capture: allocation of %zu bytes failed", rows);
+    }
+    CaptureArgs c{};
+    c.rows = (float*)s->cp_mem;
+    c.count = (unsigned*)((char*)s->cp_mem + rows);
+    c.cap = o->capacity;
+    c.fstride = o->facet_stride;
+    c.foff = o->facet_offset;
+    c.sstride = o->step_stride;
+    c.gate = GateArgs{o->kappa_t, o->kappa_c, o->damage_max};
+    HIP_TRY(hipMemsetAsync(c.count, 0, 4, s->stream));
+    s->cp = c;
+    s->cp_on = true;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_capture_end(ldpm_system* s, float* rows, int64_t max_rows, int64_t* n_rows)
+{
+    if (!s || !n_rows) return fail(LDPM_ERR_ARG, "null argument");
+    if (!s->cp_on) return fail(LDPM_ERR_STATE, "no capture in progress");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    unsigned cnt = 0;
+    HIP_TRY(hipMemcpy(&cnt, s->cp.count, 4, hipMemcpyDeviceToHost));
+    const int64_t n = std::min<int64_t>((int64_t)cnt, s->cp.cap);
+    *n_rows = (int64_t)cnt;
+    if (rows && max_rows > 0)
+        HIP_TRY(hipMemcpy(rows, s->cp.rows, (size_t)std::min(n, max_rows) * 16 * 4, hipMemcpyDeviceToHost));
+    (void)hipFree(s->cp_mem);
+    s->cp_mem = nullptr;
+    s->cp_on = false;
+    s->cp = CaptureArgs{};
+    return LDPM_OK;
+}
+
 ldpm_status ldpm_get_launch(ldpm_system* s, ldpm_launch* o)
 {
     if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
@@ -1463,6 +1777,9 @@ ldpm_status ldpm_get_launch(ldpm_system* s, ldpm_launch* o)
 void ldpm_free(ldpm_system* s)
 {
     if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->sg_mem) (void)hipFree(s->sg_mem);
+    if (s->cp_mem) (void)hipFree(s->cp_mem);
     if (s->arena) {
         (void)hipStreamSynchronize(s->stream);
         if (s->dev_free) s->dev_free(s->arena, s->alloc_ctx);

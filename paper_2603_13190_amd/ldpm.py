@@ -24,7 +24,8 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_reaction", "ldpm_get_info", "ldpm_set_launch", "ldpm_get_launch", "ldpm_autotune",
            "ldpm_free", "ldpm_mlp_num_params", "ldpm_mlp_create", "ldpm_mlp_set_data",
            "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
-           "ldpm_mlp_free",
+           "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_capture_begin",
+           "ldpm_capture_end",
            "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
@@ -90,6 +91,18 @@ class TuneTrial(C.Structure):
     _fields_ = [("launch", Launch), ("us_per_step", C.c_double)]
 
 
+class SurrogateDesc(C.Structure):
+    _fields_ = [("params", _fp), ("x_mean", C.c_float * 9), ("x_scale", C.c_float * 9),
+                ("y_scale", C.c_float * 3), ("box_lo", C.c_float * 9), ("box_hi", C.c_float * 9),
+                ("kappa_t", C.c_float), ("kappa_c", C.c_float), ("damage_max", C.c_float)]
+
+
+class CaptureOpts(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("facet_stride", C.c_int32), ("facet_offset", C.c_int32),
+                ("step_stride", C.c_int32), ("kappa_t", C.c_float), ("kappa_c", C.c_float),
+                ("damage_max", C.c_float)]
+
+
 class LdpmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"ldpm {_STATUS.get(status, status)}: {msg}")
@@ -131,6 +144,10 @@ def lib():
         L.ldpm_mlp_get_params.argtypes = [C.c_void_p, _fp]
         L.ldpm_mlp_free.argtypes = [C.c_void_p]
         L.ldpm_mlp_free.restype = None
+        L.ldpm_set_surrogate.argtypes = [C.c_void_p, C.POINTER(SurrogateDesc)]
+        L.ldpm_surrogate_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.ldpm_capture_begin.argtypes = [C.c_void_p, C.POINTER(CaptureOpts)]
+        L.ldpm_capture_end.argtypes = [C.c_void_p, _fp, C.c_int64, C.POINTER(C.c_int64)]
         L.ldpm_free.argtypes = [C.c_void_p]
         L.ldpm_free.restype = None
         L.ldpm_last_error.restype = C.c_char_p
@@ -385,6 +402,48 @@ class System:
                                  persistent=l.persistent)
         trials = [(as_dict(arr[i].launch), arr[i].us_per_step) for i in range(min(nt.value, cap))]
         return as_dict(best), us.value, trials
+
+    def set_surrogate(self, params, x_mean, x_scale, y_scale, box_lo, box_hi,
+                      kappa_t=0.8, kappa_c=0.9, damage_max=0.05):
+        """Install the MLP surrogate of the facet law (None removes it)."""
+        if params is None:
+            _check(lib().ldpm_set_surrogate(self.h, None))
+            return
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        d = SurrogateDesc()
+        d.params = p.ctypes.data_as(_fp)
+        for name, v in (("x_mean", x_mean), ("x_scale", x_scale), ("y_scale", y_scale),
+                        ("box_lo", box_lo), ("box_hi", box_hi)):
+            arr = getattr(d, name)
+            for i, x in enumerate(np.asarray(v, dtype=np.float64)):
+                arr[i] = float(x)
+        d.kappa_t, d.kappa_c, d.damage_max = float(kappa_t), float(kappa_c), float(damage_max)
+        _check(lib().ldpm_set_surrogate(self.h, C.byref(d)))
+
+    def surrogate_count(self):
+        n = C.c_int64()
+        _check(lib().ldpm_surrogate_count(self.h, C.byref(n)))
+        return int(n.value)
+
+    def capture_begin(self, capacity, facet_stride=1, facet_offset=0, step_stride=1,
+                      kappa_t=0.8, kappa_c=0.9, damage_max=0.05):
+        o = CaptureOpts(int(capacity), int(facet_stride), int(facet_offset), int(step_stride),
+                        float(kappa_t), float(kappa_c), float(damage_max))
+        self._cap = int(capacity)
+        _check(lib().ldpm_capture_begin(self.h, C.byref(o)))
+
+    def capture_end(self):
+        """Rows sorted by (step, facet): dict with x (n,9), y (n,3), step, facet."""
+        rows = np.zeros((self._cap, 16), dtype=np.float32)
+        n = C.c_int64()
+        _check(lib().ldpm_capture_end(self.h, rows.ctypes.data_as(_fp), self._cap, C.byref(n)))
+        k = min(int(n.value), self._cap)
+        rows = rows[:k]
+        key = rows[:, 12:14].copy().view(np.int64).ravel()
+        order = np.argsort(key, kind="stable")
+        rows, key = rows[order], key[order]
+        return dict(x=rows[:, :9].copy(), y=rows[:, 9:12].copy(), step=key >> 32,
+                    facet=key & 0xffffffff, offered=int(n.value))
 
     def close(self):
         if getattr(self, "h", None):
