@@ -142,6 +142,97 @@ def batched_case(args, tune):
     return rec
 
 
+def cycle_run(sysd, precision, model=None, every=1000, launch=None):
+    """Whole cyclic trajectory; nominal stress history, energy error, timing
+    (reaction sampling outside the timed spans), surrogate share."""
+    import torch
+    from paper_2603_13190_amd.ldpm import System
+    g = System(sysd, precision=precision)
+    if launch:
+        g.set_launch(**launch)
+    if model is not None:
+        model.install(g)
+    prog, area = sysd["meta"]["load_prog"], sysd["meta"]["area"]
+    total = sysd["meta"]["n_steps"]
+    F = sysd["meta"]["F"]
+    hist, handed = [], []
+    ms = 0.0
+    done = 0
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    while done < total:
+        k = min(every, total - done)
+        a.record()
+        g.step(k)
+        b.record()
+        torch.cuda.synchronize()
+        ms += a.elapsed_time(b)
+        done += k
+        hist.append(g.reaction(prog) / area)
+        if model is not None:
+            handed.append(g.surrogate_count())
+    en = g.energy()
+    g.close()
+    share = None
+    if model is not None:
+        # facet-updates carried by the surrogate (counts sampled per window)
+        share = float(np.mean([1.0 - h / F for h in handed]))
+    return dict(value=F * total / (ms * 1e-3), ms=ms, steps=total, hist=hist,
+                energy_err=en["err"], surrogate_share=share)
+
+
+def surrogate_case(args, sysd_tension, tune):
+    """Train the MLP surrogate on samples of FP64 trajectories of the
+    tension cube, a confined-compression cube and a sliding-platen cube, then
+    run the 100 x 200 mm cylinder through tension-compression cycles in FP64,
+    in the FP32 exact law and with the surrogate."""
+    from paper_2603_13190_amd import specimen as S
+    from paper_2603_13190_amd import surrogate as SG
+    t0 = time.perf_counter()
+    samples = [SG.capture(sysd_tension, 60000, facet_stride=16, step_stride=1000, capacity=400000)]
+    conf = S.confined_compression_cube(edge=50.0, d0=4.0, da=8.0, seed=2, pressure=20.0,
+                                       final_strain=2e-2, n_steps=30000)
+    samples.append(SG.capture(conf, 30000, facet_stride=4, step_stride=500, capacity=400000))
+    slide = S.sliding_compression_cube(50.0, d0=4.0, da=8.0, seed=3, rate=0.5)
+    samples.append(SG.capture(slide, 20000, facet_stride=4, step_stride=400, capacity=400000))
+    cap_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    model = SG.fit(samples, seed=0, steps=args.train_steps, batch=8192, lr=2e-3)
+    fit_s = time.perf_counter() - t0
+    log(f"surrogate: {model.n_train} training rows, loss {model.train_loss:.3e}, "
+        f"holdout rmse {model.holdout_rmse}, capture {cap_s:.1f} s, training {fit_s:.1f} s")
+    t0 = time.perf_counter()
+    cyl = S.cylinder_cycle(d0=args.cyl_d0, da=2 * args.cyl_d0, seed=1)
+    gen_s = time.perf_counter() - t0
+    m = cyl["meta"]
+    rec = {"workload": f"cylinder 100 x 200 mm, d {args.cyl_d0:g}-{2 * args.cyl_d0:g} mm, seed 1, "
+                       "2 tension-compression cycles (0.9x tensile / 0.5x compressive peak strain)",
+           "particles": m["N"], "tets": m["T"], "facets": m["F"], "steps": m["n_steps"], "dt": cyl["dt"],
+           "generation_s": gen_s, "train_rows": model.n_train, "train_steps": args.train_steps,
+           "train_loss": model.train_loss, "holdout_rmse_MPa": [float(v) for v in model.holdout_rmse],
+           "capture_s": cap_s, "training_s": fit_s,
+           "gate": {"kappa_t": 0.8, "kappa_c": 0.9, "damage_max": 0.05}}
+    r64 = cycle_run(cyl, "fp64")
+    rmx = cycle_run(cyl, "mixed")
+    rsg = cycle_run(cyl, "mixed", model=model)
+    h64 = np.array(r64["hist"])
+    for name, r in (("fp64", r64), ("mixed_exact", rmx), ("surrogate", rsg)):
+        h = np.array(r["hist"])
+        rec[name] = {"value": r["value"], "ms_per_step": r["ms"] / r["steps"], "energy_err": r["energy_err"],
+                     "peak_tension_MPa": float(h.max()), "peak_compression_MPa": float(h.min()),
+                     "peak_tension_err_vs_fp64": float(abs(h.max() - h64.max()) / abs(h64.max())),
+                     "peak_compression_err_vs_fp64": float(abs(h.min() - h64.min()) / abs(h64.min())),
+                     "stress_history_max_err_vs_fp64": float(np.abs(h - h64).max() / np.abs(h64).max())}
+        if r["surrogate_share"] is not None:
+            rec[name]["surrogate_share_of_facet_updates"] = r["surrogate_share"]
+        log(f"cylinder {name}: {r['value']:.4e} facet-upd/s, peak +{h.max():.3f}/{h.min():.3f} MPa, "
+            f"energy err {r['energy_err']:.2e}")
+    rec["surrogate"]["speedup_vs_fp64"] = rsg["value"] / r64["value"]
+    rec["surrogate"]["speedup_vs_mixed_exact"] = rsg["value"] / rmx["value"]
+    rec["mixed_exact"]["speedup_vs_fp64"] = rmx["value"] / r64["value"]
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +250,9 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-specimen batched case")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate gain test")
+    ap.add_argument("--cyl-d0", type=float, default=2.0)
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="bytes of a plain device copy to run (counter calibration)")
@@ -258,6 +352,10 @@ def main():
     # ---- batched: 64 uneven specimens in one system (window of steps) ----
     if not args.no_batch:
         out["batched"] = batched_case(args, tune)
+
+    # ---- learned surrogate: train on FP64 trajectories, gain test on the cylinder ----
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_case(args, sysd, tune)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----
     if not args.no_cpu:

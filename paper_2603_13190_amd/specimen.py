@@ -864,3 +864,54 @@ def batch_sliding_compression(n=64, seed=0, edge_range=(50.0, 100.0), d0=4.0, da
     out["meta"].update(edges=edges.tolist(), specimen_F=[s["meta"]["F"] for s in specs],
                        load_progs=[int(s["meta"]["load_prog"]) for s in specs], rate=rate)
     return out
+
+
+def cylinder_cycle(D=100.0, H=200.0, d0=2.0, da=4.0, seed=1, eps_t=1.2e-4, eps_c=1.0e-3,
+                   cycles=2, rate=0.2, mat=None, dt_fraction=0.8):
+    """Cylinder (axis z) cycled between tension and compression: bottom face
+    u_z = 0, theta_x = theta_y = 0 (centre node pinned laterally); top face
+    theta_x = theta_y = 0 and u_z following a triangle wave of nominal strain
+    rate `rate` between +eps_t H (about 0.9 of the tensile peak strain) and
+    -eps_c H (about half of the compressive peak), `cycles` times."""
+    mat = dict(MATERIAL_MB if mat is None else mat)
+    shape = Shape("cylinder", (D, H))
+    g = build_geometry(shape, d0, da, seed)
+    x = g["x0"]
+    N = x.shape[0]
+    tol = 1e-9
+    bot = np.abs(x[:, 2]) < tol
+    top = np.abs(x[:, 2] - H) < tol
+    mode = np.zeros((N, 6), np.uint8)
+    prog = -np.ones((N, 6), np.int32)
+    scale = np.zeros((N, 6))
+    P = Programs()
+    # triangle wave of the top displacement -> piecewise-constant velocity
+    v = rate * H
+    legs = []
+    for _ in range(cycles):
+        legs += [eps_t * H, -eps_c * H]
+    t_pts, v_pts = [0.0], [v]
+    u, t = 0.0, 0.0
+    for target in legs:
+        dur = abs(target - u) / v
+        sgn = 1.0 if target > u else -1.0
+        t_pts += [t + 1e-12, t + dur]
+        v_pts += [sgn * v, sgn * v]
+        t, u = t + dur, target
+    t_pts = np.array(t_pts[1:])
+    v_pts = np.array(v_pts[1:])
+    pid = P.add(np.concatenate([[0.0], t_pts, [t + 1e-9, 1e9]]),
+                np.concatenate([[v_pts[0]], v_pts, [0.0, 0.0]]) / v)
+    for f in (bot, top):
+        mode[f, 2] = 1
+        mode[f, 3:5] = 1
+    cen = np.argmin(np.where(bot, np.linalg.norm(x[:, :2] - D / 2, axis=1), np.inf))
+    mode[cen, 0:2] = 1
+    mode[cen, 5] = 1
+    prog[top, 2] = pid
+    scale[top, 2] = v
+    dt, lam = stable_dt(g, mat, dt_fraction)
+    return finalize(g, mat, mode, prog, scale, P, np.zeros((N, 6)), dt, f"cylinder{D:g}x{H:g}_s{seed}",
+                    dict(d0=d0, da=da, seed=seed, lam_max=float(lam.max()), height=H,
+                         area=np.pi * D * D / 4, load_prog=pid, total_time=float(t),
+                         n_steps=int(np.ceil(t / dt))))
