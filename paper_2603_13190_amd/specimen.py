@@ -300,6 +300,38 @@ def delaunay_tets(x, rel_vol_tol=1e-6):
     return tets[keep]
 
 
+def tet_quality(x, tets):
+    """6 sqrt(2) V / L_max^3: 1 for a regular tetrahedron, -> 0 for slivers."""
+    p = x[tets]
+    V = np.abs(np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])) / 6
+    L = np.zeros(tets.shape[0])
+    for a, b in EDGES:
+        L = np.maximum(L, np.linalg.norm(p[:, a] - p[:, b], axis=1))
+    return 6.0 * np.sqrt(2.0) * V / L ** 3
+
+
+def peel_boundary_slivers(x, tets, is_surf, qmin=0.05, max_iter=50):
+    """Remove, layer by layer, boundary tetrahedra whose four nodes all lie on
+    the specimen surface and whose quality is below qmin: the Delaunay
+    tetrahedralisation of points on a curved surface leaves thin slivers
+    spanning the hull."""
+    for _ in range(max_iter):
+        if tets.shape[0] == 0:
+            break
+        faces = np.concatenate([np.sort(tets[:, [b for b in range(4) if b != miss]], axis=1)
+                                for miss in range(4)])
+        tid = np.tile(np.arange(tets.shape[0]), 4)
+        _, inv, cnt = np.unique(faces, axis=0, return_inverse=True, return_counts=True)
+        on_bnd = np.zeros(tets.shape[0], bool)
+        on_bnd[tid[cnt[inv.ravel()] == 1]] = True
+        all_surf = is_surf[tets].all(axis=1)
+        bad = on_bnd & all_surf & (tet_quality(x, tets) < qmin)
+        if not bad.any():
+            break
+        tets = tets[~bad]
+    return tets
+
+
 def frame_from_normal(n):
     """Tangent m: normalised n x a, a the axis of smallest |n_i| (lowest index
     on ties); second tangent l = n x m."""
@@ -525,6 +557,7 @@ def build_geometry(shape: Shape, d0, da, seed, gap=0.1, rho=RHO, vol_fraction=No
     order = np.argsort(_morton_keys(x), kind="stable")
     x, diam, is_surf = x[order], diam[order], is_surf[order]
     tets = delaunay_tets(x)
+    tets = peel_boundary_slivers(x, tets, is_surf)
     # drop nodes not referenced by any tetrahedron
     used = np.zeros(x.shape[0], bool)
     used[tets.ravel()] = True

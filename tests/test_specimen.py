@@ -91,3 +91,13 @@ def test_batched_concatenation_offsets():
     assert c["facet_I"][a["meta"]["F"]:].min() >= a["meta"]["N"]
     assert np.array_equal(c["facet_tet"], np.arange(c["facet_tet"].size) // 12)
     assert c["prog_off"].size - 1 == (a["prog_off"].size - 1) + (b["prog_off"].size - 1)
+
+
+def test_cylinder_has_no_boundary_slivers():
+    """Points on a curved surface: boundary slivers spanning the hull are
+    peeled, the mesh fills the cylinder and no edge is long."""
+    g = S.build_geometry(S.Shape("cylinder", (40.0, 60.0)), 4.0, 8.0, seed=2)
+    vol = np.pi * 20.0 ** 2 * 60.0
+    assert abs(g["cell_vol"].sum() - vol) < 0.01 * vol
+    assert g["facet_len"].max() < 4 * 8.0
+    assert np.all(g["mass"] > 0)
