@@ -95,9 +95,10 @@ def test_batched_concatenation_offsets():
 
 def test_cylinder_has_no_boundary_slivers():
     """Points on a curved surface: boundary slivers spanning the hull are
-    peeled, the mesh fills the cylinder and no edge is long."""
+    peeled, the mesh fills the cylinder (up to the inscribed-polygon deficit
+    of ~22 surface nodes per ring, about 1.4 %) and no edge is long."""
     g = S.build_geometry(S.Shape("cylinder", (40.0, 60.0)), 4.0, 8.0, seed=2)
     vol = np.pi * 20.0 ** 2 * 60.0
-    assert abs(g["cell_vol"].sum() - vol) < 0.01 * vol
+    assert abs(g["cell_vol"].sum() - vol) < 0.03 * vol
     assert g["facet_len"].max() < 4 * 8.0
     assert np.all(g["mass"] > 0)
