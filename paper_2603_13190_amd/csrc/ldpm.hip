@@ -277,7 +277,6 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
 
     const int tid = threadIdx.x;
     const int64_t tet0 = blk * TB;
-    if constexpr (MODE == MODE_SURROGATE) mlp_load_bf16(sg.params, mlp_smem<NF / 64>().W, tid, NF);
     const int64_t T = na.T, N = na.N;
 
     // ---- facet data for lane tid, issued before the node gather so that
@@ -574,8 +573,24 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
                                                    ProgArgs pr, int64_t step, double dt, int remap,
                                                    SurrogateArgs sg, CaptureArgs cp)
 {
+    if constexpr (MODE == MODE_SURROGATE) mlp_load_bf16(sg.params, mlp_smem<12 * TB / 64>().W, threadIdx.x, 12 * TB);
     facet_tile<R, LAW, TB, MODE>(xcd_block(blockIdx.x, gridDim.x, remap), blockIdx.x == 0, na, fa, mat, pos,
                                  contrib, wint, pr, step, dt, sg, cp);
+}
+
+// Grid-stride loop over tiles: blocks stay resident and load the surrogate's
+// weights into LDS once instead of once per tile.
+template <typename R, int LAW, int TB, int MODE>
+__global__ __launch_bounds__(12 * TB) void k_facet_loop(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
+                                                        const int32_t* __restrict__ pos,
+                                                        R* __restrict__ contrib, double* __restrict__ wint,
+                                                        ProgArgs pr, int64_t step, double dt,
+                                                        SurrogateArgs sg, CaptureArgs cp)
+{
+    if constexpr (MODE == MODE_SURROGATE) mlp_load_bf16(sg.params, mlp_smem<12 * TB / 64>().W, threadIdx.x, 12 * TB);
+    const int64_t nb = (na.T + TB - 1) / TB;
+    for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x)
+        facet_tile<R, LAW, TB, MODE>(blk, blk == 0, na, fa, mat, pos, contrib, wint, pr, step, dt, sg, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -918,6 +933,20 @@ static void launch_facet_m(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
     ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
     const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
     const int64_t nb = (s->T + TB - 1) / TB;
+    if constexpr (MODE == MODE_SURROGATE) {
+        int per_cu = 1;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_facet_loop<R, LAW, TB, MODE>, 12 * TB, 0);
+        const int64_t G = std::min<int64_t>(nb, (int64_t)std::max(per_cu, 1) * std::max(s->n_cu, 1));
+        if (ev0)
+            hipExtLaunchKernelGGL((k_facet_loop<R, LAW, TB, MODE>), dim3((unsigned)G), dim3(12 * TB), 0, s->stream,
+                                  ev0, ev1, 0, na, fa, mat, (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr,
+                                  s->step, s->dt, s->sg, s->cp);
+        else
+            hipLaunchKernelGGL((k_facet_loop<R, LAW, TB, MODE>), dim3((unsigned)G), dim3(12 * TB), 0, s->stream, na,
+                               fa, mat, (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt, s->sg,
+                               s->cp);
+        return;
+    }
     if (ev0)
         hipExtLaunchKernelGGL((k_facet<R, LAW, TB, MODE>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, ev0, ev1,
                               0, na, fa, mat, (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt,

@@ -41,3 +41,19 @@ def confined_small(edge=30.0, seed=3, n_steps=1500):
 
 def tension_full():
     return cached("tension_full", lambda: S.tension_cube(edge=100.0, d0=4.0, da=10.0, seed=1))
+
+
+def elastic_full():
+    return cached("elastic_full", lambda: S.elastic_vibration_cube(edge=50.0, d0=4.0, da=8.0, seed=1))
+
+
+def confined_full():
+    return cached("confined_full", lambda: S.confined_compression_cube(edge=150.0, d0=4.0, da=12.0, seed=1))
+
+
+def batch_full():
+    return cached("batch_full", lambda: S.batch_sliding_compression(64, seed=0))
+
+
+def cylinder_full():
+    return cached("cylinder_full", lambda: S.cylinder_cycle(d0=2.0, da=4.0, seed=1))
