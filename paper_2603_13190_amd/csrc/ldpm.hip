@@ -1,14 +1,17 @@
 // MI355X (gfx950) explicit LDPM step behind the C-ABI of include/ldpm.h.
 //
 // Data layout in HBM (structure of arrays):
-//   particles  x0[3][N], q[6][N], v[6][N], mass[N], inertia[3][N],
+//   particles  node records [N] of 16 doubles (q[6], v[6], x0[3], pad: one
+//              128-byte line per node for the facet kernel's gather),
+//              mass[N], inertia[3][N],
 //              dof mode/program/scale [6][N], fext[6][N], w_ext[N], w_kin[N],
 //              incidence CSR: ptr[N+1]; tet-node (t, a) sits at pos[4t+a]
 //   tets       nodes[4][T], pos[4T], w_int[T],
 //              contributions [4T][6] per tet-node, stored in incidence order
 //   facets     cI[3][F], area[F], rec[F] (edge-frame id | local I,J code),
 //              history t[3][F], e_max[F]                (FP64 or FP32)
-//   edge frames n[3][E], m[3][E], len[E]  (deduplicated (n, m, len) triples)
+//   edge frames records [E] of 8 R (n[3], m[3], len, pad): one 64-byte
+//              (FP64) or 32-byte (FP32) record per deduplicated (n, m, len)
 //
 // One step = two kernels:
 //   k_facet    one block per TB tetrahedra, one lane per facet (12 TB lanes).
@@ -86,9 +89,7 @@ struct FacetArgs {
     const R* __restrict__ cI;      // [3][F]
     const R* __restrict__ area;    // [F]
     const int32_t* __restrict__ rec;  // [F]
-    const R* __restrict__ en;      // [3][E]
-    const R* __restrict__ em;      // [3][E]
-    const R* __restrict__ elen;    // [E]
+    const R* __restrict__ frame;   // [E][8]: n[3], m[3], len, pad
     R* __restrict__ ht;            // [3][F]
     R* __restrict__ hemax;         // [F]
     int64_t F, E;
@@ -96,9 +97,7 @@ struct FacetArgs {
 
 struct NodeArgs {
     const int32_t* __restrict__ tet;  // [4][T]
-    const double* __restrict__ x0;    // [3][N]
-    const double* __restrict__ q;     // [6][N]
-    const double* __restrict__ v;     // [6][N]
+    const double* __restrict__ node;  // [N][16]: q[6], v[6], x0[3], pad
     int64_t N, T;
 };
 
@@ -153,8 +152,7 @@ struct CaptureArgs {
 };
 
 struct ParticleArgs {
-    double* __restrict__ q;           // [6][N]
-    double* __restrict__ v;           // [6][N]
+    double* __restrict__ node;        // [N][16]: q[6], v[6], x0[3], pad
     const double* __restrict__ mass;  // [N]
     const double* __restrict__ inertia;  // [3][N]
     const uint8_t* __restrict__ mode;    // [6][N]
@@ -292,9 +290,10 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
         const int64_t F = fa.F, E = fa.E;
         rc = fa.rec[f];
         const int64_t r = rc & 0x0fffffff;
-        n0 = fa.en[r]; n1 = fa.en[E + r]; n2 = fa.en[2 * E + r];
-        m0 = fa.em[r]; m1 = fa.em[E + r]; m2 = fa.em[2 * E + r];
-        len = fa.elen[r];
+        const R* fr = fa.frame + r * 8;
+        n0 = fr[0]; n1 = fr[1]; n2 = fr[2];
+        m0 = fr[3]; m1 = fr[4]; m2 = fr[5];
+        len = fr[6];
         cI0 = fa.cI[f]; cI1 = fa.cI[F + f]; cI2 = fa.cI[2 * F + f];
         A = fa.area[f];
         tv[0] = fa.ht[f]; tv[1] = fa.ht[F + f]; tv[2] = fa.ht[2 * F + f];
@@ -323,11 +322,11 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
         if (tt < T) {
             const int64_t nd = na.tet[(int64_t)a * T + tt];
 #pragma unroll
-            for (int c = 0; c < 3; c++) s_x[c][tid] = na.x0[c * N + nd];
+            for (int c = 0; c < 6; c++) s_q[c][tid] = na.node[nd * 16 + c];
 #pragma unroll
-            for (int c = 0; c < 6; c++) s_q[c][tid] = na.q[c * N + nd];
+            for (int c = 0; c < 6; c++) s_v[c][tid] = na.node[nd * 16 + 6 + c];
 #pragma unroll
-            for (int c = 0; c < 6; c++) s_v[c][tid] = na.v[c * N + nd];
+            for (int c = 0; c < 3; c++) s_x[c][tid] = na.node[nd * 16 + 12 + c];
         }
     }
     __syncthreads();
@@ -621,9 +620,9 @@ __device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& p
     const int32_t pg = pa.prog[id];
     const uint8_t md = pa.mode[id];
     const double scl = pa.scale[id];
-    const double vold = pa.v[id];
+    const double vold = pa.node[I * 16 + 6 + d];
     const double fold = pa.fext[id];
-    const double qold = pa.q[id];
+    const double qold = pa.node[I * 16 + d];
     double f[6] = {0, 0, 0, 0, 0, 0};
     const int32_t s0 = pa.ptr[I], s1 = pa.ptr[I + 1];
     for (int32_t s = s0 + lane; s < s1; s += PG) {
@@ -659,8 +658,8 @@ __device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& p
         const double vb = (n == 0) ? vold : 0.5 * (vold + vnew);
         wk = 0.5 * M * vb * vb;
         pa.fext[id] = Fd;
-        pa.v[id] = vnew;
-        pa.q[id] = qold + dt * vnew;
+        pa.node[I * 16 + 6 + d] = vnew;
+        pa.node[I * 16 + d] = qold + dt * vnew;
         bad = !isfinite(vnew);
     }
     // energies of the particle: DoFs summed in order 0..5 by lane 0
@@ -819,13 +818,13 @@ struct ldpm_system {
     ldpm_launch launch{16, 256, 1, 0};
     int n_cu = 0;
     // device pointers
-    double *x0, *q, *v, *mass, *inertia, *scale, *body, *fext, *wext, *wkin, *wint;
+    double *node, *mass, *inertia, *scale, *body, *fext, *wext, *wkin, *wint;
     uint8_t* mode;
     int32_t *prog, *ptr, *pos, *tet, *rec, *flag;
     unsigned* bar;
     int64_t* prog_off;
     double *prog_t, *prog_v, *progv, *red;
-    void *cI, *area, *en, *em, *elen, *ht, *hemax, *contrib;
+    void *cI, *area, *frame, *ht, *hemax, *contrib;
     int64_t n_prog_pts = 0, n_prog = 0;
     MatDev<double> matd;
     MatDev<float> matf;
@@ -927,9 +926,9 @@ size_t rbytes(int prec) { return prec == LDPM_PREC_MIXED ? 4 : 8; }
 template <typename R, int LAW, int TB, int MODE>
 static void launch_facet_m(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    NodeArgs na{s->tet, s->x0, s->q, s->v, s->N, s->T};
-    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->en, (const R*)s->em,
-                    (const R*)s->elen, (R*)s->ht, (R*)s->hemax, s->F, s->E};
+    NodeArgs na{s->tet, s->node, s->N, s->T};
+    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->frame, (R*)s->ht, (R*)s->hemax,
+                    s->F, s->E};
     ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
     const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
     const int64_t nb = (s->T + TB - 1) / TB;
@@ -998,7 +997,7 @@ static void launch_facet(ldpm_system* s, hipEvent_t ev0 = nullptr, hipEvent_t ev
 template <typename R>
 static void launch_particle_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    ParticleArgs pa{s->q,    s->v,    s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
+    ParticleArgs pa{s->node, s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
                     s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N};
     const int th = s->launch.particle_threads;
     const unsigned nb = (unsigned)((s->N * PG + th - 1) / th);
@@ -1032,11 +1031,11 @@ static hipError_t launch_persist_t(ldpm_system* s, int64_t nsteps)
     const int64_t np = (s->N * PG + 12 * TB - 1) / (12 * TB);
     int64_t G = (int64_t)per_cu * s->n_cu;
     G = std::min<int64_t>(G, std::max<int64_t>(nb, np));
-    NodeArgs na{s->tet, s->x0, s->q, s->v, s->N, s->T};
-    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->en, (const R*)s->em,
-                    (const R*)s->elen, (R*)s->ht, (R*)s->hemax, s->F, s->E};
+    NodeArgs na{s->tet, s->node, s->N, s->T};
+    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->frame, (R*)s->ht, (R*)s->hemax,
+                    s->F, s->E};
     ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
-    ParticleArgs pa{s->q,    s->v,    s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
+    ParticleArgs pa{s->node, s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
                     s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N};
     GridSync gs{s->bar, s->bar + 1, s->flag};
     MatDev<R> mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
@@ -1215,13 +1214,6 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
         rec[f] = (int32_t)((uint32_t)r | ((uint32_t)aI << 28) | ((uint32_t)aJ << 30));
     }
     const int64_t E = (int64_t)el.size();
-    // SoA frames [3][E]
-    std::vector<double> enS(3 * E), emS(3 * E);
-    for (int64_t r = 0; r < E; r++)
-        for (int c = 0; c < 3; c++) {
-            enS[c * E + r] = en[3 * r + c];
-            emS[c * E + r] = em[3 * r + c];
-        }
     // ---- incidence CSR: slots 4t+a in ascending order ----
     std::vector<int32_t> ptr(N + 1, 0), slot(4 * T), pos(4 * T);
     for (int64_t t = 0; t < T; t++)
@@ -1257,7 +1249,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     const int prec = d->precision;
     const size_t rb = rbytes(prec);
     Carve cv;
-    const size_t o_x0 = cv.take<double>(3 * N), o_q = cv.take<double>(6 * N), o_v = cv.take<double>(6 * N);
+    const size_t o_node = cv.take<double>(16 * N);
     const size_t o_mass = cv.take<double>(N), o_in = cv.take<double>(3 * N), o_scale = cv.take<double>(6 * N);
     const size_t o_body = body.empty() ? 0 : cv.take<double>(6 * N);
     const size_t o_fext = cv.take<double>(6 * N), o_wext = cv.take<double>(N), o_wkin = cv.take<double>(N);
@@ -1273,11 +1265,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     cv.off = (cv.off + 255) & ~size_t(255);
     const size_t o_area = cv.off; cv.off += F * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
-    const size_t o_en = cv.off; cv.off += 3 * E * rb;
-    cv.off = (cv.off + 255) & ~size_t(255);
-    const size_t o_em = cv.off; cv.off += 3 * E * rb;
-    cv.off = (cv.off + 255) & ~size_t(255);
-    const size_t o_el = cv.off; cv.off += E * rb;
+    const size_t o_frame = cv.off; cv.off += 8 * E * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
     const size_t o_ht = cv.off; cv.off += 3 * F * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
@@ -1309,7 +1297,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->arena = base;
     s->arena_bytes = total;
     char* B = (char*)base;
-    s->x0 = (double*)(B + o_x0); s->q = (double*)(B + o_q); s->v = (double*)(B + o_v);
+    s->node = (double*)(B + o_node);
     s->mass = (double*)(B + o_mass); s->inertia = (double*)(B + o_in); s->scale = (double*)(B + o_scale);
     s->body = body.empty() ? nullptr : (double*)(B + o_body);
     s->fext = (double*)(B + o_fext); s->wext = (double*)(B + o_wext); s->wkin = (double*)(B + o_wkin);
@@ -1320,7 +1308,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->prog_off = (int64_t*)(B + o_poff); s->prog_t = (double*)(B + o_pt); s->prog_v = (double*)(B + o_pv);
     s->red = (double*)(B + o_red);
     s->progv = (double*)(B + o_progv);
-    s->cI = B + o_cI; s->area = B + o_area; s->en = B + o_en; s->em = B + o_em; s->elen = B + o_el;
+    s->cI = B + o_cI; s->area = B + o_area; s->frame = B + o_frame;
     s->ht = B + o_ht; s->hemax = B + o_hem; s->contrib = B + o_con;
 
     auto H2D = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -1344,9 +1332,15 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
         return fail(LDPM_ERR_ARG, "non-finite initial state");
     }
 #define CK(x) do { e = (x); if (e != hipSuccess) { ldpm_free(s); return fail(LDPM_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e)); } } while (0)
-    CK(H2D(s->x0, d->x0, 3 * N * 8));
-    CK(H2D(s->q, q0, 6 * N * 8));
-    CK(H2D(s->v, v0, 6 * N * 8));
+    std::vector<double> nodes((size_t)16 * N, 0.0);
+    for (int64_t i = 0; i < N; i++) {
+        for (int c = 0; c < 6; c++) {
+            nodes[16 * i + c] = q0[c * N + i];
+            nodes[16 * i + 6 + c] = v0[c * N + i];
+        }
+        for (int c = 0; c < 3; c++) nodes[16 * i + 12 + c] = d->x0[c * N + i];
+    }
+    CK(H2D(s->node, nodes.data(), 16 * N * 8));
     CK(H2D(s->mass, d->mass, N * 8));
     CK(H2D(s->inertia, d->rot_inertia, 3 * N * 8));
     CK(H2D(s->scale, d->dof_scale, 6 * N * 8));
@@ -1366,9 +1360,15 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     }
     CK(put_r(s->cI, d->facet_cI, 3 * F));
     CK(put_r(s->area, d->facet_area, F));
-    CK(put_r(s->en, enS.data(), 3 * E));
-    CK(put_r(s->em, emS.data(), 3 * E));
-    CK(put_r(s->elen, el.data(), E));
+    std::vector<double> frec((size_t)8 * E, 0.0);
+    for (int64_t r = 0; r < E; r++) {
+        for (int c = 0; c < 3; c++) {
+            frec[8 * r + c] = en[3 * r + c];
+            frec[8 * r + 3 + c] = em[3 * r + c];
+        }
+        frec[8 * r + 6] = el[r];
+    }
+    CK(put_r(s->frame, frec.data(), 8 * E));
     // history, accumulators
     std::vector<double> zF(3 * F, 0.0);
     CK(put_r(s->ht, (is && is->t) ? is->t : zF.data(), 3 * F));
@@ -1466,8 +1466,15 @@ ldpm_status ldpm_read_state(ldpm_system* s, ldpm_state* o)
     ldpm_status st = ldpm_sync(s);
     if (st != LDPM_OK && st != LDPM_ERR_UNSTABLE) return st;
     const int64_t N = s->N, T = s->T, F = s->F;
-    if (o->q) HIP_TRY(hipMemcpy(o->q, s->q, 6 * N * 8, hipMemcpyDeviceToHost));
-    if (o->v) HIP_TRY(hipMemcpy(o->v, s->v, 6 * N * 8, hipMemcpyDeviceToHost));
+    if (o->q || o->v) {
+        std::vector<double> nodes((size_t)16 * N);
+        HIP_TRY(hipMemcpy(nodes.data(), s->node, 16 * N * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < N; i++)
+            for (int c = 0; c < 6; c++) {
+                if (o->q) o->q[c * N + i] = nodes[16 * i + c];
+                if (o->v) o->v[c * N + i] = nodes[16 * i + 6 + c];
+            }
+    }
     if (o->fext) HIP_TRY(hipMemcpy(o->fext, s->fext, 6 * N * 8, hipMemcpyDeviceToHost));
     if (o->w_int) HIP_TRY(hipMemcpy(o->w_int, s->wint, T * 8, hipMemcpyDeviceToHost));
     if (o->w_ext) HIP_TRY(hipMemcpy(o->w_ext, s->wext, N * 8, hipMemcpyDeviceToHost));
@@ -1541,7 +1548,7 @@ ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
     //   contributions written 24R; particles: x0, q, v read (15 doubles)
     const double hist = (s->law == 1 ? 4.0 : 3.0) * rb;
     o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + 2.0 * hist) + E * 7.0 * rb + T * (16.0 + 16.0 + 16.0 + 24.0 * rb) +
-                            N * 15.0 * 8.0;
+                            N * 15.0 * 8.0;  // frames: 7 of 8 words used; nodes: 15 of 16
     // particle kernel: contributions 24R per tet read; per particle ptr 4 B,
     //   q, v, fext read + written (3 x 6 x 16 B), mass + inertia 32 B, scale 48 B,
     //   prog 24 B, mode 6 B, w_ext r+w 16 B, w_kin 8 B
@@ -1596,7 +1603,7 @@ std::vector<Region> dynamic_regions(ldpm_system* s)
 {
     const size_t rb = rbytes(s->prec);
     const size_t N = (size_t)s->N, T = (size_t)s->T, F = (size_t)s->F;
-    return {{s->q, 6 * N * 8}, {s->v, 6 * N * 8},   {s->fext, 6 * N * 8}, {s->wext, N * 8},
+    return {{s->node, 16 * N * 8}, {s->fext, 6 * N * 8}, {s->wext, N * 8},
             {s->wkin, N * 8},  {s->wint, T * 8},    {s->ht, 3 * F * rb},  {s->hemax, F * rb}};
 }
 }  // namespace
