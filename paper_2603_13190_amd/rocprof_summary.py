@@ -3,6 +3,7 @@
   python -m paper_2603_13190_amd.rocprof_summary stats  <kernel_stats.csv> <out.txt> <command...>
   python -m paper_2603_13190_amd.rocprof_summary pmc    <fetch_counter_collection.csv>
          <write_counter_collection.csv> <out.json> <calibration_bytes> <command...>
+  python -m paper_2603_13190_amd.rocprof_summary counters <counter_collection.csv> <out.txt> <command...>
 
 The PMC mode reads FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the facet
 kernels and of the calibration copy kernel (a plain device-to-device copy of
@@ -106,11 +107,37 @@ def pmc(fetch_csv, write_csv, out_path, calib_bytes, command):
     print(json.dumps(out, indent=1))
 
 
+def counters(csv_path, out_path, command):
+    """Per-kernel average of every counter in one --pmc pass, with the
+    per-wave figures (instructions and cycles divided by SQ_WAVES)."""
+    per = defaultdict(lambda: defaultdict(list))
+    for r in _rows(csv_path):
+        cn = r.get("Counter_Name") or r.get("CounterName")
+        name = _short(r.get("Kernel_Name") or r.get("KernelName") or r.get("Name"))
+        per[name][cn].append(float(r.get("Counter_Value") or r.get("CounterValue")))
+    lines = [f"command: {command}", f"source: {os.path.basename(csv_path)} (rocprofv3 --pmc)",
+             f"kernel sources sha1: {source_sha1()}", ""]
+    for k in sorted(per):
+        if "k_" not in k:
+            continue
+        avg = {c: sum(v) / len(v) for c, v in per[k].items()}
+        waves = avg.get("SQ_WAVES")
+        lines.append(f"{k}  ({max(len(v) for v in per[k].values())} dispatches)")
+        for c in sorted(avg):
+            extra = f"   {avg[c] / waves:12.1f} per wave" if waves and c != "SQ_WAVES" else ""
+            lines.append(f"  {c:24s} {avg[c]:16.1f}{extra}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "stats":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif mode == "pmc":
         pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], " ".join(sys.argv[6:]))
+    elif mode == "counters":
+        counters(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     else:
         raise SystemExit(__doc__)
