@@ -271,7 +271,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     __shared__ R s_MI[3][NF];
     __shared__ R s_MJ[3][NF];
     __shared__ double s_w[NF];
-    __shared__ uint8_t s_code[NF];
+    __shared__ __align__(4) uint8_t s_code[NF];
 
     const int tid = threadIdx.x;
     const int64_t tet0 = blk * TB;
@@ -534,22 +534,22 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
         const int64_t tt = tet0 + tl;
         if (tt < T) {
             R acc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+            // the tet's 12 codes in three words, then branch-free selects so
+            // that every LDS read can be issued up front
+            const uint32_t* cw = reinterpret_cast<const uint32_t*>(s_code) + tl * 3;
+            const uint32_t w0 = cw[0], w1 = cw[1], w2 = cw[2];
 #pragma unroll
             for (int j = 0; j < 12; j++) {
                 const int fl = tl * 12 + j;
-                const int cd = s_code[fl];
-                if ((cd & 3) == a) {
+                const int cd = (int)(((j < 4 ? w0 : (j < 8 ? w1 : w2)) >> (8 * (j & 3))) & 0xff);
+                const bool onI = (cd & 3) == a;
+                const bool onJ = ((cd >> 2) & 3) == a;
 #pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        acc[c] += s_F[c][fl];
-                        acc[3 + c] += s_MI[c][fl];
-                    }
-                } else if (((cd >> 2) & 3) == a) {
-#pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        acc[c] -= s_F[c][fl];
-                        acc[3 + c] -= s_MJ[c][fl];
-                    }
+                for (int c = 0; c < 3; c++) {
+                    const R f = s_F[c][fl];
+                    const R mm = onI ? s_MI[c][fl] : s_MJ[c][fl];
+                    acc[c] = onI ? acc[c] + f : (onJ ? acc[c] - f : acc[c]);
+                    acc[3 + c] = onI ? acc[3 + c] + mm : (onJ ? acc[3 + c] - mm : acc[3 + c]);
                 }
             }
             R* out = contrib + (int64_t)opos * 6;
