@@ -39,6 +39,22 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def gen_confined150():
+    from paper_2603_13190_amd import specimen as S
+    t = time.perf_counter()
+    s = S.confined_compression_cube(edge=150.0, d0=4.0, da=12.0, seed=1)
+    s["meta"]["generation_s"] = time.perf_counter() - t
+    return s
+
+
+def gen_cylinder(d0):
+    from paper_2603_13190_amd import specimen as S
+    t = time.perf_counter()
+    s = S.cylinder_cycle(d0=d0, da=2 * d0, seed=1)
+    s["meta"]["generation_s"] = time.perf_counter() - t
+    return s
+
+
 def timed_run(sysd, precision, warmup, steps, launch=None, tune=None):
     import torch
     from paper_2603_13190_amd.ldpm import System
@@ -191,18 +207,19 @@ def surrogate_case(args, sysd_tension, tune):
     from paper_2603_13190_amd import specimen as S
     from paper_2603_13190_amd import surrogate as SG
     t0 = time.perf_counter()
-    samples = [SG.capture(sysd_tension, 60000, facet_stride=16, step_stride=1000, capacity=400000)]
+    samples = [SG.capture(sysd_tension, 60000, facet_stride=16, step_stride=1000, capacity=4000000)]
     conf = S.confined_compression_cube(edge=50.0, d0=4.0, da=8.0, seed=2, pressure=20.0,
                                        final_strain=2e-2, n_steps=30000)
-    samples.append(SG.capture(conf, 30000, facet_stride=4, step_stride=500, capacity=400000))
+    samples.append(SG.capture(conf, 30000, facet_stride=4, step_stride=500, capacity=4000000))
     slide = S.sliding_compression_cube(50.0, d0=4.0, da=8.0, seed=3, rate=0.5)
-    samples.append(SG.capture(slide, 20000, facet_stride=4, step_stride=400, capacity=400000))
+    samples.append(SG.capture(slide, 20000, facet_stride=4, step_stride=400, capacity=4000000))
     cap_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     model = SG.fit(samples, seed=0, steps=args.train_steps, batch=8192, lr=2e-3)
     fit_s = time.perf_counter() - t0
     log(f"surrogate: {model.n_train} training rows, loss {model.train_loss:.3e}, "
-        f"holdout rmse {model.holdout_rmse}, capture {cap_s:.1f} s, training {fit_s:.1f} s")
+        f"holdout rmse {model.holdout_rmse}, dead zone {model.y_dead}, capture {cap_s:.1f} s, "
+        f"training {fit_s:.1f} s")
     t0 = time.perf_counter()
     cyl = S.cylinder_cycle(d0=args.cyl_d0, da=2 * args.cyl_d0, seed=1)
     gen_s = time.perf_counter() - t0
@@ -212,6 +229,7 @@ def surrogate_case(args, sysd_tension, tune):
            "particles": m["N"], "tets": m["T"], "facets": m["F"], "steps": m["n_steps"], "dt": cyl["dt"],
            "generation_s": gen_s, "train_rows": model.n_train, "train_steps": args.train_steps,
            "train_loss": model.train_loss, "holdout_rmse_MPa": [float(v) for v in model.holdout_rmse],
+           "dead_zone_MPa": [float(v) for v in model.y_dead],
            "capture_s": cap_s, "training_s": fit_s,
            "gate": {"kappa_t": 0.8, "kappa_c": 0.9, "damage_max": 0.05}}
     r64 = cycle_run(cyl, "fp64")
@@ -227,11 +245,58 @@ def surrogate_case(args, sysd_tension, tune):
                      "stress_history_max_err_vs_fp64": float(np.abs(h - h64).max() / np.abs(h64).max())}
         if r["surrogate_share"] is not None:
             rec[name]["surrogate_share_of_facet_updates"] = r["surrogate_share"]
+        share = "" if r["surrogate_share"] is None else f", surrogate share {r['surrogate_share']:.3f}"
         log(f"cylinder {name}: {r['value']:.4e} facet-upd/s, peak +{h.max():.3f}/{h.min():.3f} MPa, "
-            f"energy err {r['energy_err']:.2e}")
+            f"energy err {r['energy_err']:.2e}{share}")
     rec["surrogate"]["speedup_vs_fp64"] = rsg["value"] / r64["value"]
     rec["surrogate"]["speedup_vs_mixed_exact"] = rsg["value"] / rmx["value"]
     rec["mixed_exact"]["speedup_vs_fp64"] = rmx["value"] / r64["value"]
+    return rec, model
+
+
+def window_case(sysd, workload, runs, warmup, steps, tune):
+    """Throughput of `steps` explicit steps after `warmup` steps from the
+    initial state, per precision (and with the surrogate when a model is
+    given), with the facet kernel's HBM rate from HIP-event kernel times."""
+    import torch
+    from paper_2603_13190_amd.ldpm import System
+    m = sysd["meta"]
+    F = m["F"]
+    rec = {"workload": workload, "particles": m["N"], "tets": m["T"], "facets": F, "dt": sysd["dt"],
+           "warmup": warmup, "steps": steps, "generation_s": m.get("generation_s")}
+    for name, prec, model in runs:
+        g = System(sysd, precision=prec)
+        r = {}
+        if model is None and tune:
+            best, us, trials = g.autotune(steps_per_trial=tune)
+            r["launch"] = best
+        if model is not None:
+            model.install(g)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.step(steps)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        r.update(value=F * steps / (ms * 1e-3), ms_per_step=ms / steps, energy_err=g.energy()["err"])
+        if model is None:
+            g.set_launch(**dict(g.get_launch(), persistent=0))
+            info = g.info()
+            fms, _ = g.step_profiled(100)
+            favg = fms / 100
+            r.update(facet_kernel_avg_us=favg * 1e3,
+                     facet_kernel_GBs=info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9,
+                     facet_kernel_frac_hbm=info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9 / PEAK_HBM_GBS)
+        else:
+            r["surrogate_share_of_facets_at_end"] = 1.0 - g.surrogate_count() / F
+        g.close()
+        rec[name] = r
+        extra = f", facet kernel {r['facet_kernel_GBs']:.0f} GB/s" if "facet_kernel_GBs" in r else \
+            f", surrogate share at end {r['surrogate_share_of_facets_at_end']:.3f}"
+        log(f"{workload.split(',')[0]} {name}: {r['value']:.4e} facet-upd/s{extra}")
     return rec
 
 
@@ -255,6 +320,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate gain test")
     ap.add_argument("--cyl-d0", type=float, default=2.0)
     ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 150 mm confined cube and the full-size cylinder windows")
+    ap.add_argument("--cyl-full-d0", type=float, default=1.1)
+    ap.add_argument("--large-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="bytes of a plain device copy to run (counter calibration)")
@@ -266,6 +335,14 @@ def main():
 
     import numpy as np
     import torch
+    pool, futs = None, {}
+    if not args.no_large:
+        # large specimens are generated on the host while the GPU runs the
+        # other cases (workers forked before the GPU is initialised)
+        import concurrent.futures as cf
+        pool = cf.ProcessPoolExecutor(max_workers=2)
+        futs["confined"] = pool.submit(gen_confined150)
+        futs["cylinder"] = pool.submit(gen_cylinder, args.cyl_full_d0)
     torch.cuda.init()
     sysd, desc, total = make_workload(args.workload)
     steps = args.steps if args.steps is not None else total - args.warmup
@@ -306,14 +383,14 @@ def main():
                    "trajectory_steps": args.warmup + steps, "launch": launch,
                    "autotune": getattr(g64, "tuned", None)},
         "energy_balance_err": en64["err"],
-        "roofline": {"bound": "hbm", "kernel": "k_facet<double,1,%d>" % args.tets_per_block,
+        "roofline": {"bound": "hbm", "kernel": "k_facet<double,1,%d>" % launch["tets_per_block"],
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "alg_bytes_per_launch": info["facet_kernel_bytes"],
                      "avg_launch_us": favg * 1e3, "particle_kernel_avg_us": pavg * 1e3},
     }
 
-    traffic = measured_traffic(args.workload, "k_facet<double, 1, %d>" % args.tets_per_block)
+    traffic = measured_traffic(args.workload, "k_facet<double, 1, %d>" % launch["tets_per_block"])
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
 
@@ -356,8 +433,27 @@ def main():
         out["batched"] = batched_case(args, tune)
 
     # ---- learned surrogate: train on FP64 trajectories, gain test on the cylinder ----
+    model = None
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_case(args, sysd, tune)
+        out["surrogate"], model = surrogate_case(args, sysd, tune)
+
+    # ---- large single specimens: 150 mm confined cube, full-size cylinder ----
+    if futs:
+        conf = futs["confined"].result()
+        out["confined150"] = window_case(
+            conf, "confined compression, 150 mm cube, d 4-12 mm, seed 1, 20 MPa lateral pressure "
+                  "then axial shortening", [("fp64", "fp64", None), ("mixed", "mixed", None)],
+            2000, args.large_steps, tune)
+        del conf
+        cyl = futs["cylinder"].result()
+        runs = [("fp64", "fp64", None), ("mixed_exact", "mixed", None)]
+        if model is not None:
+            runs.append(("surrogate", "mixed", model))
+        out["cylinder_full"] = window_case(
+            cyl, f"cylinder 100 x 200 mm, d {args.cyl_full_d0:g}-{2 * args.cyl_full_d0:g} mm, seed 1, "
+                 "window in the first tension leg", runs, 3000, args.large_steps, tune)
+        del cyl
+        pool.shutdown()
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----
     if not args.no_cpu:

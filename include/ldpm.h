@@ -265,12 +265,18 @@ void ldpm_mlp_free(ldpm_mlp *m);
 /* ---- Surrogate of the facet law inside the step ----------------------------
  * With a surrogate installed (precision MIXED, law 1), every facet that is
  * inside the network's envelope and has not been handed back is updated by
- * t = t_old + E de + y_scale * MLP(x_hat) instead of the exact law, where
- * x are the facet's features in the frame aligned with its trial shear
- * traction t_old,T + alpha E0 de_T:
+ * t = t_old + E de + s * (y_scale * MLP(x_hat)) instead of the exact law,
+ * where s = |t_old + E de| + y_tau is the magnitude of the elastic trial
+ * traction (E = E0 diag(1, alpha, alpha)), x are the facet's features in
+ * the frame aligned with its trial shear traction t_old,T + alpha E0 de_T:
  *   x = [de_N, de_par, de_perp, e_N, e_par, e_perp, t_N, t_par, t_perp]_old,
  * x_hat = (x - x_mean) * x_scale, and the output is the traction residual
- * over the elastic predictor in the same frame.  A facet is handed back to
+ * over the elastic predictor in the same frame, relative to s.  Each
+ * relative residual component whose magnitude is below y_dead (the
+ * network's error floor on samples whose exact residual vanishes, e.g.
+ * elastic facets) is taken as exactly zero, so that such facets follow the
+ * elastic predictor without drift.
+ * A facet is handed back to
  * the exact FP32 law for good (sticky flag) when
  *   - a feature leaves [box_lo, box_hi] (the trained range), or
  *   - tension: its effective strain reaches kappa_t e0(omega), or its e_max
@@ -284,6 +290,8 @@ void ldpm_mlp_free(ldpm_mlp *m);
 typedef struct {
     const float *params;                    /* [ldpm_mlp_num_params()] FP32, copied */
     float x_mean[9], x_scale[9], y_scale[3];
+    float y_dead[3];                        /* >= 0; 0 disables the dead zone */
+    float y_tau;                            /* >= 0 (MPa): floor of the residual scale s */
     float box_lo[9], box_hi[9];
     float kappa_t, kappa_c, damage_max;
 } ldpm_surrogate;
@@ -297,7 +305,8 @@ ldpm_status ldpm_surrogate_count(ldpm_system *s, int64_t *n_exact);
  * f % facet_stride == facet_offset that are inside the envelope (same
  * criteria as above with kappa_t, kappa_c, damage_max), one row of 16 floats:
  * x[9] (features as above), the exact residual t - (t_old + E de) in the
- * aligned frame [3], and the key n * 2^32 + f as an int64 in floats 12-13.
+ * aligned frame [3] (absolute, MPa), the key n * 2^32 + f as an int64 in
+ * floats 12-13, and |t_old + E de| in float 14 (float 15 is 0).
  * Rows land in arrival order; sort by key for a reproducible order.        */
 typedef struct {
     int64_t capacity;         /* rows */

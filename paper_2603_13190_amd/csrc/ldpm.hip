@@ -139,7 +139,8 @@ struct GateArgs {
 struct SurrogateArgs {
     const float* __restrict__ params;  // [MLP_NPARAM] FP32
     uint8_t* __restrict__ flag;        // [F] sticky: 1 = handed back to the exact law
-    float xmean[MLP_IN], xscale[MLP_IN], yscale[MLP_OUT], lo[MLP_IN], hi[MLP_IN];
+    float xmean[MLP_IN], xscale[MLP_IN], yscale[MLP_OUT], ydead[MLP_OUT], lo[MLP_IN], hi[MLP_IN];
+    float ytau;
     GateArgs gate;
 };
 
@@ -219,6 +220,15 @@ __device__ __forceinline__ float facet_damage(const MatDev<R>& p, const R e[3], 
     const R eff = d_ldexp(seff, ex);
     const R teff = d_sqrt(t[0] * t[0] + (t[1] * t[1] + t[2] * t[2]) * p.inv_alpha);
     return (float)(R(1) - teff / (p.E0 * eff));
+}
+
+// |t_old + E de|: magnitude of the elastic trial traction, the scale of a
+// facet's surrogate residual
+template <typename R>
+__device__ __forceinline__ float trial_norm(const MatDev<R>& p, const R told[3], const R de[3])
+{
+    const R a = told[0] + p.E0 * de[0], b = told[1] + p.aE0 * de[1], c = told[2] + p.aE0 * de[2];
+    return (float)d_sqrt(a * a + b * b + c * c);
 }
 
 // surrogate features (aligned with the trial shear traction) of a facet
@@ -443,10 +453,16 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                 __builtin_amdgcn_wave_barrier();
                 mlp_forward_wave(sm.W, buf, sm.out[w]);
                 if (use_nn) {
-                    // traction = elastic predictor + scaled residual, back in (n, m, l)
-                    const float r0 = sm.out[w][lane * 4 + 0] * sg.yscale[0];
-                    const float r1 = sm.out[w][lane * 4 + 1] * sg.yscale[1];
-                    const float r2 = sm.out[w][lane * 4 + 2] * sg.yscale[2];
+                    // traction = elastic predictor + residual, the residual
+                    // relative to s = |t_old + E de| + tau; below the
+                    // network's error floor a relative residual is zero
+                    const float s_tr = trial_norm(mat, told, de) + sg.ytau;
+                    float r0 = sm.out[w][lane * 4 + 0] * sg.yscale[0];
+                    float r1 = sm.out[w][lane * 4 + 1] * sg.yscale[1];
+                    float r2 = sm.out[w][lane * 4 + 2] * sg.yscale[2];
+                    r0 = (fabsf(r0) < sg.ydead[0] ? 0.f : r0) * s_tr;
+                    r1 = (fabsf(r1) < sg.ydead[1] ? 0.f : r1) * s_tr;
+                    r2 = (fabsf(r2) < sg.ydead[2] ? 0.f : r2) * s_tr;
                     float rM, rL;
                     from_frame(fr, r1, r2, rM, rL);
                     R tn[3];
@@ -495,7 +511,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                     const int64_t key = step * 4294967296ll + f;
                     row[12] = __int_as_float((int)(key & 0xffffffff));
                     row[13] = __int_as_float((int)(key >> 32));
-                    row[14] = 0.f;
+                    row[14] = trial_norm(mat, told, de);
                     row[15] = 0.f;
                 }
             }
@@ -1732,7 +1748,14 @@ ldpm_status ldpm_set_surrogate(ldpm_system* s, const ldpm_surrogate* g)
         a.lo[k] = g->box_lo[k];
         a.hi[k] = g->box_hi[k];
     }
-    for (int k = 0; k < MLP_OUT; k++) a.yscale[k] = g->y_scale[k];
+    for (int k = 0; k < MLP_OUT; k++) {
+        if (!(std::isfinite(g->y_dead[k]) && g->y_dead[k] >= 0.f))
+            return fail(LDPM_ERR_ARG, "surrogate: y_dead[%d] must be finite and >= 0", k);
+        a.yscale[k] = g->y_scale[k];
+        a.ydead[k] = g->y_dead[k];
+    }
+    if (!(std::isfinite(g->y_tau) && g->y_tau >= 0.f)) return fail(LDPM_ERR_ARG, "surrogate: y_tau must be finite and >= 0");
+    a.ytau = g->y_tau;
     a.gate = GateArgs{g->kappa_t, g->kappa_c, g->damage_max};
     HIP_TRY(hipMemcpyAsync((void*)a.params, g->params, (size_t)MLP_NPARAM * 4, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemsetAsync(a.flag, 0, (size_t)s->F, s->stream));

@@ -46,8 +46,15 @@ struct MlpBf16 {
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 __device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
 
-// Accurate single-precision tanh (ocml).
-__device__ __forceinline__ float act_tanh(float x) { return tanhf(x); }
+// tanh x = 1 - 2 / (2^(2 x log2 e) + 1) on the transcendental unit (exp2 and
+// reciprocal, each about 1 ulp): absolute error ~1e-7, below the BF16
+// rounding the activations then undergo; saturates to +-1 through exp2's
+// overflow to +inf and underflow to 0.  Training and inference share it.
+__device__ __forceinline__ float act_tanh(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
+    return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+}
 
 // C[64 x 16*NT] tile loop for one wave: A rows from A (pitch pa), B given
 // transposed as Bt (row n holds column n of B, pitch pb), KT steps of 32.

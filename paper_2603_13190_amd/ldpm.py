@@ -93,7 +93,8 @@ class TuneTrial(C.Structure):
 
 class SurrogateDesc(C.Structure):
     _fields_ = [("params", _fp), ("x_mean", C.c_float * 9), ("x_scale", C.c_float * 9),
-                ("y_scale", C.c_float * 3), ("box_lo", C.c_float * 9), ("box_hi", C.c_float * 9),
+                ("y_scale", C.c_float * 3), ("y_dead", C.c_float * 3),
+                ("y_tau", C.c_float), ("box_lo", C.c_float * 9), ("box_hi", C.c_float * 9),
                 ("kappa_t", C.c_float), ("kappa_c", C.c_float), ("damage_max", C.c_float)]
 
 
@@ -404,7 +405,7 @@ class System:
         return as_dict(best), us.value, trials
 
     def set_surrogate(self, params, x_mean, x_scale, y_scale, box_lo, box_hi,
-                      kappa_t=0.8, kappa_c=0.9, damage_max=0.05):
+                      kappa_t=0.8, kappa_c=0.9, damage_max=0.05, y_dead=(0.0, 0.0, 0.0), y_tau=0.0):
         """Install the MLP surrogate of the facet law (None removes it)."""
         if params is None:
             _check(lib().ldpm_set_surrogate(self.h, None))
@@ -413,11 +414,12 @@ class System:
         d = SurrogateDesc()
         d.params = p.ctypes.data_as(_fp)
         for name, v in (("x_mean", x_mean), ("x_scale", x_scale), ("y_scale", y_scale),
-                        ("box_lo", box_lo), ("box_hi", box_hi)):
+                        ("y_dead", y_dead), ("box_lo", box_lo), ("box_hi", box_hi)):
             arr = getattr(d, name)
             for i, x in enumerate(np.asarray(v, dtype=np.float64)):
                 arr[i] = float(x)
         d.kappa_t, d.kappa_c, d.damage_max = float(kappa_t), float(kappa_c), float(damage_max)
+        d.y_tau = float(y_tau)
         _check(lib().ldpm_set_surrogate(self.h, C.byref(d)))
 
     def surrogate_count(self):
@@ -433,7 +435,8 @@ class System:
         _check(lib().ldpm_capture_begin(self.h, C.byref(o)))
 
     def capture_end(self):
-        """Rows sorted by (step, facet): dict with x (n,9), y (n,3), step, facet."""
+        """Rows sorted by (step, facet): dict with x (n,9), y (n,3) (absolute
+        residuals), s (n,) (|t_old + E de|), step, facet."""
         rows = np.zeros((self._cap, 16), dtype=np.float32)
         n = C.c_int64()
         _check(lib().ldpm_capture_end(self.h, rows.ctypes.data_as(_fp), self._cap, C.byref(n)))
@@ -442,7 +445,7 @@ class System:
         key = rows[:, 12:14].copy().view(np.int64).ravel()
         order = np.argsort(key, kind="stable")
         rows, key = rows[order], key[order]
-        return dict(x=rows[:, :9].copy(), y=rows[:, 9:12].copy(), step=key >> 32,
+        return dict(x=rows[:, :9].copy(), y=rows[:, 9:12].copy(), s=rows[:, 14].copy(), step=key >> 32,
                     facet=key & 0xffffffff, offered=int(n.value))
 
     def close(self):

@@ -40,6 +40,7 @@ from __future__ import annotations
 import dataclasses
 import hashlib
 import math
+import os
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
@@ -310,6 +311,12 @@ def tet_quality(x, tets):
     return 6.0 * np.sqrt(2.0) * V / L ** 3
 
 
+def _triple_key(tri, n):
+    """One int64 per row of sorted node triples (values < n <= 2^21)."""
+    t = tri.astype(np.int64)
+    return (t[:, 0] * n + t[:, 1]) * n + t[:, 2]
+
+
 def peel_boundary_slivers(x, tets, is_surf, qmin=0.05, max_iter=50):
     """Remove, layer by layer, boundary tetrahedra whose four nodes all lie on
     the specimen surface and whose quality is below qmin: the Delaunay
@@ -321,7 +328,7 @@ def peel_boundary_slivers(x, tets, is_surf, qmin=0.05, max_iter=50):
         faces = np.concatenate([np.sort(tets[:, [b for b in range(4) if b != miss]], axis=1)
                                 for miss in range(4)])
         tid = np.tile(np.arange(tets.shape[0]), 4)
-        _, inv, cnt = np.unique(faces, axis=0, return_inverse=True, return_counts=True)
+        _, inv, cnt = np.unique(_triple_key(faces, x.shape[0]), return_inverse=True, return_counts=True)
         on_bnd = np.zeros(tets.shape[0], bool)
         on_bnd[tid[cnt[inv.ravel()] == 1]] = True
         all_surf = is_surf[tets].all(axis=1)
@@ -478,52 +485,58 @@ def _skew(c):
                      np.stack([-c[..., 1], c[..., 0], z], -1)], -2)
 
 
-def element_lambda_max(sysd, E0, alpha, chunk=20000):
+def element_lambda_max(sysd, E0, alpha, chunk=8192, workers=None):
     """Largest eigenvalue of each tetrahedron's elastic operator with its
     share of the lumped mass; the max over tetrahedra bounds the assembled
-    system's largest eigenvalue from above."""
+    system's largest eigenvalue from above.
+
+    Facet k couples the 6-DoF blocks of its nodes I and J through
+    B = [-1, S(c^I) | 1, -S(c^J)] (jump = B q) and D = E0 (alpha 1 + (1 - alpha) n n^T):
+    K_tet = sum_k (A_k / l_k) B^T D B.  Chunks run on a thread pool (the
+    batched products and eigvalsh release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
     tets = sysd["tet_nodes"].astype(np.int64)
     T = tets.shape[0]
     mshare = sysd["_elem_mass"]
     lam = np.empty(T)
     fI = sysd["facet_I"].reshape(T, 12)
     ga = tets[:, FACET_LOCAL[:, 0]]
-    gb = tets[:, FACET_LOCAL[:, 1]]
     locI = np.where(fI == ga, FACET_LOCAL[None, :, 0], FACET_LOCAL[None, :, 1])
     locJ = np.where(fI == ga, FACET_LOCAL[None, :, 1], FACET_LOCAL[None, :, 0])
     cI = sysd["facet_cI"].reshape(T, 12, 3)
     n = sysd["facet_n"].reshape(T, 12, 3)
     ln = sysd["facet_len"].reshape(T, 12)
     A = sysd["facet_area"].reshape(T, 12)
-    for s0 in range(0, T, chunk):
+    eye3 = np.eye(3)
+
+    def one(s0):
         s1 = min(T, s0 + chunk)
         t = s1 - s0
-        K = np.zeros((t, 24, 24))
+        rows = np.arange(t)
+        K = np.zeros((t, 4, 6, 4, 6))
         for j in range(12):
             nn = n[s0:s1, j]
             cj = cI[s0:s1, j] - ln[s0:s1, j, None] * nn
-            B = np.zeros((t, 3, 24))
-            eye = np.broadcast_to(np.eye(3), (t, 3, 3))
-            li = locI[s0:s1, j]
-            lj = locJ[s0:s1, j]
-            rows = np.arange(t)
-            for d in range(3):
-                for k in range(3):
-                    B[rows, d, 6 * li + k] = -eye[:, d, k]
-                    B[rows, d, 6 * lj + k] = eye[:, d, k]
-            SI = _skew(cI[s0:s1, j])
-            SJ = _skew(cj)
-            for d in range(3):
-                for k in range(3):
-                    B[rows, d, 6 * li + 3 + k] = SI[:, d, k]
-                    B[rows, d, 6 * lj + 3 + k] = -SJ[:, d, k]
-            D = E0 * (alpha * np.eye(3)[None] + (1 - alpha) * np.einsum("ti,tj->tij", nn, nn))
-            w = (A[s0:s1, j] / ln[s0:s1, j])[:, None, None]
-            K += w * np.einsum("tai,tab,tbj->tij", B, D, B)
-        m = mshare[s0:s1].reshape(t, 24)
-        wgt = 1.0 / np.sqrt(m)
+            GI = np.concatenate([np.broadcast_to(-eye3, (t, 3, 3)), _skew(cI[s0:s1, j])], axis=2)
+            GJ = np.concatenate([np.broadcast_to(eye3, (t, 3, 3)), -_skew(cj)], axis=2)
+            D = E0 * (alpha * eye3[None] + (1 - alpha) * nn[:, :, None] * nn[:, None, :])
+            D *= (A[s0:s1, j] / ln[s0:s1, j])[:, None, None]
+            DI, DJ = D @ GI, D @ GJ
+            GIt, GJt = GI.transpose(0, 2, 1), GJ.transpose(0, 2, 1)
+            li, lj = locI[s0:s1, j], locJ[s0:s1, j]
+            K[rows, li, :, li, :] += GIt @ DI
+            K[rows, li, :, lj, :] += GIt @ DJ
+            K[rows, lj, :, li, :] += GJt @ DI
+            K[rows, lj, :, lj, :] += GJt @ DJ
+        K = K.reshape(t, 24, 24)
+        wgt = 1.0 / np.sqrt(mshare[s0:s1].reshape(t, 24))
         Kh = K * wgt[:, :, None] * wgt[:, None, :]
         lam[s0:s1] = np.linalg.eigvalsh(Kh)[:, -1]
+
+    starts = range(0, T, chunk)
+    nw = workers or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=nw) as ex:
+        list(ex.map(one, starts))
     return lam
 
 
@@ -537,7 +550,7 @@ def boundary_triangles(tets):
         faces.append(np.concatenate([f, tets[:, miss:miss + 1]], axis=1))
     F = np.concatenate(faces, axis=0)
     key = np.sort(F[:, :3], axis=1)
-    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    _, inv, cnt = np.unique(_triple_key(key, int(tets.max()) + 1), return_inverse=True, return_counts=True)
     once = cnt[inv.ravel()] == 1
     return F[once]
 

@@ -70,6 +70,10 @@ def test_capture_rows_match_oracle_law():
         print("feature group", g0, "max err / scale", err[:, g0:g0 + 3].max() / scale)
         assert err[:, g0:g0 + 3].max() <= 1e-5 * scale
     tsc = np.abs(told).max()
+    # residual scale |t_old + E de| (float 14 of a row)
+    ttr = told[fac] + p["E0"] * np.array([1, p["alpha"], p["alpha"]]) * (e[fac] - eo[fac])
+    s_ref = np.linalg.norm(ttr, axis=1)
+    assert np.abs(rows["s"][sel] - s_ref).max() <= 1e-6 * s_ref.max()
     assert np.abs(rows["y"][sel][:, 0] - r[:, 0]).max() <= 1e-6 * tsc
     assert np.abs(rows["y"][sel][:, 1] - rp).max() <= 1e-6 * tsc
     assert np.abs(rows["y"][sel][:, 2] - rq).max() <= 1e-6 * tsc
