@@ -201,8 +201,8 @@ typedef struct {
 } ldpm_info;
 ldpm_status ldpm_get_info(ldpm_system *s, ldpm_info *out);
 
-/* Launch configuration of the step: tetrahedra per facet block (16, 32 or
- * 64), threads per particle block (64..1024, multiple of 64), whether the
+/* Launch configuration of the step: tetrahedra per facet block (8, 16, 32
+ * or 64), threads per particle block (64..1024, multiple of 64), whether the
  * facet kernel's tiles are remapped so that each XCD (own L2) works on a
  * contiguous range, and whether ldpm_step runs as one persistent
  * cooperative launch per chunk of steps (facet and particle phases separated

@@ -978,8 +978,12 @@ static void launch_facet_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
     if constexpr (LAW == 1 && std::is_same<R, double>::value) {
         if (s->cp_on) return launch_facet_m<R, LAW, TB, MODE_CAPTURE>(s, ev0, ev1);
     }
-    if constexpr (LAW == 1 && std::is_same<R, float>::value && TB <= 32) {
+    if constexpr (LAW == 1 && std::is_same<R, float>::value && TB >= 16 && TB <= 32) {
         if (s->sg_on) return launch_facet_m<R, LAW, TB, MODE_SURROGATE>(s, ev0, ev1);
+    }
+    if constexpr (LAW == 1 && std::is_same<R, float>::value && TB == 8) {
+        // the surrogate's tiles need whole waves (8-tet tiles have 1.5)
+        if (s->sg_on) return launch_facet_m<R, LAW, 16, MODE_SURROGATE>(s, ev0, ev1);
     }
     if constexpr (LAW == 1 && std::is_same<R, float>::value && TB == 64) {
         // the surrogate's weights and activation tiles do not fit next to a
@@ -993,6 +997,7 @@ template <typename R, int LAW>
 static void launch_facet_l(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (s->launch.tets_per_block) {
+    case 8: launch_facet_t<R, LAW, 8>(s, ev0, ev1); break;
     case 32: launch_facet_t<R, LAW, 32>(s, ev0, ev1); break;
     case 64: launch_facet_t<R, LAW, 64>(s, ev0, ev1); break;
     default: launch_facet_t<R, LAW, 16>(s, ev0, ev1); break;
@@ -1077,6 +1082,7 @@ template <typename R, int LAW>
 static hipError_t launch_persist_l(ldpm_system* s, int64_t n)
 {
     switch (s->launch.tets_per_block) {
+    case 8: return launch_persist_t<R, LAW, 8>(s, n);
     case 32: return launch_persist_t<R, LAW, 32>(s, n);
     case 64: return launch_persist_t<R, LAW, 64>(s, n);
     default: return launch_persist_t<R, LAW, 16>(s, n);
@@ -1576,8 +1582,8 @@ ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
 ldpm_status ldpm_set_launch(ldpm_system* s, const ldpm_launch* c)
 {
     if (!s || !c) return fail(LDPM_ERR_ARG, "null argument");
-    if (c->tets_per_block != 16 && c->tets_per_block != 32 && c->tets_per_block != 64)
-        return fail(LDPM_ERR_ARG, "tets_per_block must be 16, 32 or 64");
+    if (c->tets_per_block != 8 && c->tets_per_block != 16 && c->tets_per_block != 32 && c->tets_per_block != 64)
+        return fail(LDPM_ERR_ARG, "tets_per_block must be 8, 16, 32 or 64");
     if (c->particle_threads < 64 || c->particle_threads > 1024 || c->particle_threads % 64)
         return fail(LDPM_ERR_ARG, "particle_threads must be a multiple of 64 in [64, 1024]");
     s->launch = *c;
@@ -1665,13 +1671,13 @@ ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* 
     hipEvent_t a = nullptr, b = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    const int tbs[3] = {16, 32, 64};
+    const int tbs[4] = {8, 16, 32, 64};
     const int pts[4] = {64, 128, 256, 512};
     std::vector<ldpm_launch> cands;
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 4; i++)
         for (int j = 0; j < 4; j++)
             for (int rm = 0; rm < 2; rm++) cands.push_back(ldpm_launch{tbs[i], pts[j], rm, 0});
-    for (int i = 0; i < 3; i++) cands.push_back(ldpm_launch{tbs[i], 256, 0, 1});
+    for (int i = 0; i < 4; i++) cands.push_back(ldpm_launch{tbs[i], 256, 0, 1});
     double best_t = 1e300;
     ldpm_launch best_l = keep;
     int32_t nt = 0;
