@@ -284,7 +284,8 @@ void ldpm_mlp_free(ldpm_mlp *m);
  *   - compression: -e_DV reaches kappa_c e_c0 or -t_N reaches kappa_c sigma_c0
  *     (onset of pore collapse), or
  *   - the damage D = 1 - t / (E0 e) of the surrogate's traction exceeds
- *     damage_max.
+ *     damage_max (D is taken as 0 while e < 0.01 sigma_t / E0, where the
+ *     ratio is rounding noise).
  * NULL removes the surrogate.  (For callers comparing a learned law with the
  * exact one; the exact law stays the reference.)                           */
 typedef struct {

@@ -209,7 +209,10 @@ __device__ __forceinline__ bool in_envelope(const MatDev<R>& p, const R e[3], R 
     return (-eDV < (R)g.kappa_c * p.ec0) && (-told[0] < (R)g.kappa_c * p.sigma_c0);
 }
 
-// damage D = 1 - t/(E0 e) of a tensile facet (0 in compression)
+// damage D = 1 - t/(E0 e) of a tensile facet; 0 in compression and while
+// the effective strain is below 1 % of sigma_t/E0, where the ratio is a
+// ratio of rounding errors (e.g. ahead of a stress wave) and the facet is
+// far from any damage
 template <typename R>
 __device__ __forceinline__ float facet_damage(const MatDev<R>& p, const R e[3], const R t[3])
 {
@@ -218,6 +221,7 @@ __device__ __forceinline__ float facet_damage(const MatDev<R>& p, const R e[3], 
     int ex;
     scaled_norm(e[0], e[1], e[2], p.alpha, sN, sT2, seff, seff2, ex);
     const R eff = d_ldexp(seff, ex);
+    if (eff < R(0.01) * p.sigma_t * p.inv_E0) return 0.f;
     const R teff = d_sqrt(t[0] * t[0] + (t[1] * t[1] + t[2] * t[2]) * p.inv_alpha);
     return (float)(R(1) - teff / (p.E0 * eff));
 }

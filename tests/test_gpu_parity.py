@@ -70,6 +70,19 @@ def test_one_step_maps_tension(n_before):
     compare(g, o, tol=TOL_STEP, what=f"tension after {n_before}")
 
 
+def test_one_step_map_tension_with_reload_rule():
+    """k_t = 0.5 (reload from e_tr = k_t (e_max - sigma_bt/E0) after unloading):
+    one step from a post-peak oracle state."""
+    s = dict(tension_small())
+    s["material"] = dict(s["material"], k_t=0.5)
+    o = O.Oracle(s).step(900)
+    assert (o.emax > s["material"]["sigma_t"] / s["material"]["E0"]).any()
+    g = gpu(s, init_state=oracle_state(o))
+    o.step(1)
+    g.step(1)
+    compare(g, o, tol=TOL_STEP, what="tension k_t = 0.5 after 900")
+
+
 @pytest.mark.parametrize("n_before", [300, 900, 1400])
 def test_one_step_maps_confined_compression(n_before):
     s = confined_small()

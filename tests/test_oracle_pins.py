@@ -255,6 +255,26 @@ def test_central_difference_stability_limit():
     assert res[1.01] > 1e6
 
 
+def test_central_difference_is_time_reversible():
+    """The central-difference (leapfrog) scheme is time reversible: from
+    (q^{n+1}, -v^{n+3/2}) the elastic system retraces its path and returns
+    to q^1 (after the start-up half step), up to rounding."""
+    s = small_cube()
+    o = O.Oracle(s).step(1)
+    q1 = o.q.copy()
+    n = 400
+    o.step(n)
+    qn = o.q.copy()
+    state = (o.t.copy(), o.e.copy(), o.emax.copy(), o.fext.copy())
+    o.step(1)
+    vnext = o.v.copy()
+    o.set_state(qn, -vnext, *state, step=n + 1)
+    o.step(n)
+    scale = np.abs(qn - q1).max()
+    assert scale > 0
+    assert np.abs(o.q - q1).max() < 1e-9 * scale
+
+
 def test_elastic_work_equals_strain_energy():
     """With t = E e and the trapezoid rule per facet, the accumulated internal
     work equals the strain energy 1/2 sum A l e.E e of the last strains."""
@@ -390,6 +410,39 @@ def test_tension_unloading_is_elastic_to_zero():
     expect = np.maximum(tpk - p["E0"] * (3e-4 - down), 0.0)
     assert np.abs(tdown - expect).max() < 1e-9 * p["sigma_t"]
     assert tdown[-1] == 0.0
+
+
+def test_tension_reload_starts_at_e_tr():
+    """Unload/reload rule with k_t > 0 (appendix, fracturing behaviour):
+    after softening to e_max and unloading to zero traction, a pure-tension
+    reload stays at zero traction up to e_tr = k_t (e_max - sigma_bt/E0) and
+    then rises with slope E0, capped by sigma_bt(e_max) =
+    sigma_t exp(-H_t (e_max - sigma_t/E0) / sigma_t).  The path stays in
+    tension (e_N > 0): a visit to e_N <= 0 would switch to the compressive
+    branch, whose incremental traction the next tensile step carries over as
+    the previous effective traction."""
+    p = dict(MB, k_t=0.5)
+    L = 6.0
+    emax, elow = 3e-4, 1e-6
+    up = np.linspace(0, emax, 301)[1:]
+    down = np.linspace(emax, elow, 300)[1:]
+    again = np.linspace(elow, emax, 3000)[1:]
+    path = np.zeros((up.size + down.size + again.size, 3))
+    path[:, 0] = np.concatenate([up, down, again])
+    T, EM = O.drive_facet(p, L, path)
+    Ht = 2 * p["E0"] / (p["l_t"] / L - 1)
+    e0 = p["sigma_t"] / p["E0"]
+    sbt = p["sigma_t"] * math.exp(-Ht * (emax - e0) / p["sigma_t"])
+    etr = p["k_t"] * (emax - sbt / p["E0"])
+    assert elow < etr < emax
+    t_re = T[up.size + down.size:, 0]
+    expect = np.minimum(p["E0"] * np.maximum(again - etr, 0.0), sbt)
+    assert np.abs(t_re - expect).max() < 1e-9 * p["sigma_t"]
+    assert EM[-1] == emax
+    # k_t = 0: e_tr = 0, the reload is elastic from the lowest strain reached
+    T0, _ = O.drive_facet(dict(MB), L, path)
+    t0 = T0[up.size + down.size:, 0]
+    assert np.abs(t0 - np.minimum(p["E0"] * (again - elow), sbt)).max() < 1e-9 * p["sigma_t"]
 
 
 def test_hydrostatic_compression_closed_form():
