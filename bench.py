@@ -383,14 +383,14 @@ def main():
                    "trajectory_steps": args.warmup + steps, "launch": launch,
                    "autotune": getattr(g64, "tuned", None)},
         "energy_balance_err": en64["err"],
-        "roofline": {"bound": "hbm", "kernel": "k_facet<double,1,%d>" % launch["tets_per_block"],
+        "roofline": {"bound": "hbm", "kernel": "k_facet<double, 1, %d, 0>" % launch["tets_per_block"],
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "alg_bytes_per_launch": info["facet_kernel_bytes"],
                      "avg_launch_us": favg * 1e3, "particle_kernel_avg_us": pavg * 1e3},
     }
 
-    traffic = measured_traffic(args.workload, "k_facet<double, 1, %d>" % launch["tets_per_block"])
+    traffic = measured_traffic(args.workload, "k_facet<double, 1, %d, 0>" % launch["tets_per_block"])
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
 
