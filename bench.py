@@ -36,6 +36,10 @@ def make_workload(name):
     if name == "tension_cube50":
         s = S.tension_cube(edge=50.0, d0=4.0, da=8.0, seed=1, rate=5e-2, ramp=1e-3)
         return s, "uniaxial tension, 50 mm cube, d 4-8 mm, seed 1", 20000
+    if name == "batch64":
+        s = S.batch_sliding_compression(64, seed=0)
+        return s, ("64 x unconfined compression, sliding platens, edge U(50,100) mm, d 4-8 mm, "
+                   "strain rate 2.5e-2 /s, seeds 0..63 (one batched system)"), 2000
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -409,7 +413,7 @@ def main():
         log(f"mixed: {vmx:.4e} facet-upd/s, speedup {vmx / v64:.2f}x")
 
     # ---- accuracy: nominal stress histories, FP64 vs mixed ----
-    if not args.no_accuracy:
+    if not args.no_accuracy and "load_prog" in sysd["meta"]:
         every = max(1, (args.warmup + steps) // 100)
         h64, e64, g = accuracy_run(sysd, "fp64", args.warmup + steps, every, launch)
         g.close()
