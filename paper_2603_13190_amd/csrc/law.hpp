@@ -25,6 +25,8 @@ __device__ __forceinline__ float d_frexp(float x, int* e) { return frexpf(x, e);
 __device__ __forceinline__ double d_ldexp(double x, int e) { return ldexp(x, e); }
 __device__ __forceinline__ float d_ldexp(float x, int e) { return ldexpf(x, e); }
 __device__ __forceinline__ double d_abs(double x) { return fabs(x); }
+__device__ __forceinline__ double d_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float d_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ float d_abs(float x) { return fabsf(x); }
 
 // |(a, b, c)| weighted as sqrt(a^2 + w (b^2 + c^2)), returned as the scaled

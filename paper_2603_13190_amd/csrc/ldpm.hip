@@ -297,7 +297,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     const bool fvalid = (tid < NF) && (tet0 + ftl < T);
     const int64_t f = (tet0 + ftl) * 12 + (tid % 12);
     int32_t rc = 0;
-    R n0 = 0, n1 = 0, n2 = 0, m0 = 0, m1 = 0, m2 = 0, len = 1, cI0 = 0, cI1 = 0, cI2 = 0, A = 0;
+    R n0 = 0, n1 = 0, n2 = 0, m0 = 0, m1 = 0, m2 = 0, len = 1, ilen = 1, cI0 = 0, cI1 = 0, cI2 = 0, A = 0;
     R tv[3] = {R(0), R(0), R(0)};
     R emx = R(0);
     if (fvalid) {
@@ -308,6 +308,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
         n0 = fr[0]; n1 = fr[1]; n2 = fr[2];
         m0 = fr[3]; m1 = fr[4]; m2 = fr[5];
         len = fr[6];
+        ilen = fr[7];
         cI0 = fa.cI[f]; cI1 = fa.cI[F + f]; cI2 = fa.cI[2 * F + f];
         A = fa.area[f];
         tv[0] = fa.ht[f]; tv[1] = fa.ht[F + f]; tv[2] = fa.ht[2 * F + f];
@@ -413,7 +414,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                 dv[1] = dv1 + (wJ2 * cJ0 - wJ0 * cJ2) - (wI2 * cI0 - wI0 * cI2);
                 dv[2] = dv2 + (wJ0 * cJ1 - wJ1 * cJ0) - (wI0 * cI1 - wI1 * cI0);
             }
-            const R il = R(1) / len;
+            const R il = ilen;
             e[0] = (n0 * d[0] + n1 * d[1] + n2 * d[2]) * il;
             e[1] = (m0 * d[0] + m1 * d[1] + m2 * d[2]) * il;
             e[2] = (l0 * d[0] + l1 * d[1] + l2 * d[2]) * il;
@@ -554,8 +555,9 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
         const int64_t tt = tet0 + tl;
         if (tt < T) {
             R acc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-            // the tet's 12 codes in three words, then branch-free selects so
-            // that every LDS read can be issued up front
+            // the tet's 12 codes in three words; each facet adds sg * value
+            // with sg = +1 (node on the I side), -1 (J side) or 0 (not on the
+            // facet): fma(+-1, x, acc) rounds like acc +- x
             const uint32_t* cw = reinterpret_cast<const uint32_t*>(s_code) + tl * 3;
             const uint32_t w0 = cw[0], w1 = cw[1], w2 = cw[2];
 #pragma unroll
@@ -564,12 +566,12 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                 const int cd = (int)(((j < 4 ? w0 : (j < 8 ? w1 : w2)) >> (8 * (j & 3))) & 0xff);
                 const bool onI = (cd & 3) == a;
                 const bool onJ = ((cd >> 2) & 3) == a;
+                const R sg = onI ? R(1) : (onJ ? R(-1) : R(0));
+                const R* mrow = onI ? &s_MI[0][fl] : &s_MJ[0][fl];
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    const R f = s_F[c][fl];
-                    const R mm = onI ? s_MI[c][fl] : s_MJ[c][fl];
-                    acc[c] = onI ? acc[c] + f : (onJ ? acc[c] - f : acc[c]);
-                    acc[3 + c] = onI ? acc[3 + c] + mm : (onJ ? acc[3 + c] - mm : acc[3 + c]);
+                    acc[c] = d_fma(sg, s_F[c][fl], acc[c]);
+                    acc[3 + c] = d_fma(sg, mrow[c * NF], acc[3 + c]);
                 }
             }
             R* out = contrib + (int64_t)opos * 6;
@@ -1393,6 +1395,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
             frec[8 * r + 3 + c] = em[3 * r + c];
         }
         frec[8 * r + 6] = el[r];
+        frec[8 * r + 7] = 1.0 / el[r];
     }
     CK(put_r(s->frame, frec.data(), 8 * E));
     // history, accumulators
@@ -1570,11 +1573,12 @@ ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
     const double N = (double)s->N, T = (double)s->T, F = (double)s->F, E = (double)s->E;
     // facet kernel: each array touched once per launch
     //   facets: rec 4 B + cI 3R + area R + history (t 3R + e_max R) read and written
-    //   edge frames 7R per frame; tets: nodes 16 B, pos 16 B, w_int 16 B (r+w),
-    //   contributions written 24R; particles: x0, q, v read (15 doubles)
+    //   edge frames 8R per frame (n, m, l, 1/l); tets: nodes 16 B, pos 16 B,
+    //   w_int 16 B (r+w), contributions written 24R; particles: x0, q, v read
+    //   (15 doubles)
     const double hist = (s->law == 1 ? 4.0 : 3.0) * rb;
-    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + 2.0 * hist) + E * 7.0 * rb + T * (16.0 + 16.0 + 16.0 + 24.0 * rb) +
-                            N * 15.0 * 8.0;  // frames: 7 of 8 words used; nodes: 15 of 16
+    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + 2.0 * hist) + E * 8.0 * rb + T * (16.0 + 16.0 + 16.0 + 24.0 * rb) +
+                            N * 15.0 * 8.0;  // nodes: 15 of 16 words used
     // particle kernel: contributions 24R per tet read; per particle ptr 4 B,
     //   q, v, fext read + written (3 x 6 x 16 B), mass + inertia 32 B, scale 48 B,
     //   prog 24 B, mode 6 B, w_ext r+w 16 B, w_kin 8 B
