@@ -16,6 +16,8 @@ __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_exp(double x) { return exp(x); }
 __device__ __forceinline__ float d_exp(float x) { return expf(x); }
+__device__ __forceinline__ double d_log(double x) { return log(x); }
+__device__ __forceinline__ float d_log(float x) { return logf(x); }
 __device__ __forceinline__ double d_atan2(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float d_atan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double d_pow(double x, double y) { return pow(x, y); }
@@ -33,10 +35,19 @@ __device__ __forceinline__ float d_abs(float x) { return fabsf(x); }
 // value sv, its square sv2 and the exponent ex with value = sv * 2^ex.  The
 // power-of-two rescaling is exact, so in the normal range the result equals
 // the plain formula bit for bit; it only prevents squares of tiny strains
-// from underflowing (e = 0 while e_N > 0).
+// from underflowing in FP32 (e = 0 while e_N > 0).  In FP64 the squares of
+// any strain above 1e-150 are normal, so the plain formula is used (ex = 0).
 template <typename R>
 __device__ __forceinline__ void scaled_norm(R a, R b, R c, R w, R& sa, R& sbc2, R& sv, R& sv2, int& ex)
 {
+    if constexpr (sizeof(R) == 8) {
+        ex = 0;
+        sa = a;
+        sbc2 = b * b + c * c;
+        sv2 = a * a + w * sbc2;
+        sv = d_sqrt(sv2);
+        return;
+    }
     R mx = d_abs(a);
     mx = d_abs(b) > mx ? d_abs(b) : mx;
     mx = d_abs(c) > mx ? d_abs(c) : mx;
@@ -102,7 +113,8 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
         if (over > R(0)) {  // softening started: exp(-H0 <e_max - e0> / sigma0)
             const R omega = d_atan2(sN, d_sqrt(al * sT2));
             const R Ht = R(2) * p.E0 / (p.l_t / len - R(1));
-            const R H0 = p.Hs_over_alpha + (Ht - p.Hs_over_alpha) * d_pow(p.two_over_pi * omega, p.n_t);
+            // (2 omega / pi)^n_t for a base in [0, 1] (0 -> exp(-inf) = 0)
+            const R H0 = p.Hs_over_alpha + (Ht - p.Hs_over_alpha) * d_exp(p.n_t * d_log(p.two_over_pi * omega));
             sbt = sigma0 * d_exp(-H0 * over / sigma0);
         }
         const R etr = p.k_t * (em - sbt * p.inv_E0);
