@@ -344,7 +344,13 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
             for (int c = 0; c < 3; c++) s_x[c][tid] = na.node[nd * 16 + 12 + c];
         }
     }
-    __syncthreads();
+    if constexpr (NS <= 64) {
+        // staging and phase B are both done by wave 0, whose LDS accesses
+        // complete in program order: a code-motion fence suffices
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
 
     // ---- B: e_V contribution grad N_a . u_a of node a of tet tl ----
     if (tid < NS) {
