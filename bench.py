@@ -93,14 +93,21 @@ def accuracy_run(sysd, precision, total, every, launch=None):
         g.set_launch(**launch)
     prog = sysd["meta"]["load_prog"]
     area = sysd["meta"]["area"]
-    hist = []
+    hist, kin = [], []
     done = 0
     while done < total:
         k = min(every, total - done)
         g.step(k)
         done += k
         hist.append(g.reaction(prog) / area)
+        e = g.energy()
+        kin.append(e["W_kin"] / e["W_int"] if e["W_int"] > 0 else float("nan"))
     en = g.energy()
+    # quasi-static check (kinetic over internal energy), after the first
+    # tenth of the run (the loading ramp) and at the end
+    tail = kin[len(kin) // 10:]
+    en["kin_over_int_max_after_ramp"] = float(np.nanmax(tail)) if tail else float("nan")
+    en["kin_over_int_end"] = float(kin[-1]) if kin else float("nan")
     return hist, en, g
 
 
@@ -419,6 +426,10 @@ def main():
         g.close()
         peak64 = max(h64)
         out["peak_stress_fp64_MPa"] = peak64
+        out["quasi_static"] = {"kin_over_int_max_after_ramp": e64["kin_over_int_max_after_ramp"],
+                               "kin_over_int_end": e64["kin_over_int_end"]}
+        log(f"quasi-static: W_kin/W_int max after the ramp {e64['kin_over_int_max_after_ramp']:.2e}, "
+            f"at the end {e64['kin_over_int_end']:.2e}")
         if not args.no_mixed:
             hmx, emx, g = accuracy_run(sysd, "mixed", args.warmup + steps, every, launch)
             g.close()

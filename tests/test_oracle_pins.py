@@ -170,6 +170,36 @@ def test_stiffness_symmetric_with_six_rigid_modes():
     assert w[6] > 1e-6 * w[-1]
 
 
+def test_dense_stiffness_assembled_in_numpy_equals_the_oracle():
+    """Brute force: K assembled densely from the virtual work of each facet,
+    K = sum_k (A_k / l_k) B_k^T E0 (alpha 1 + (1 - alpha) n n^T) B_k with the
+    jump [[u]] = B_k q = u_J + th_J x c^J - u_I - th_I x c^I (eq. strain1,
+    c^J = c^I - l n), equals the oracle's matrix-free internal force."""
+    s = few()
+    orc = O.Oracle(s)
+    N = orc.N
+    p = s["material"]
+    E0, al = p["E0"], p["alpha"]
+
+    def skew(c):
+        return np.array([[0, -c[2], c[1]], [c[2], 0, -c[0]], [-c[1], c[0], 0]])
+    K = np.zeros((6 * N, 6 * N))
+    for k in range(s["facet_I"].size):
+        I, J = int(s["facet_I"][k]), int(s["facet_J"][k])
+        n = s["facet_n"][k]
+        cI = s["facet_cI"][k]
+        cJ = cI - s["facet_len"][k] * n
+        B = np.zeros((3, 6 * N))
+        B[:, 6 * I:6 * I + 3] = -np.eye(3)
+        B[:, 6 * I + 3:6 * I + 6] = skew(cI)       # -th_I x c^I = c^I x th_I
+        B[:, 6 * J:6 * J + 3] = np.eye(3)
+        B[:, 6 * J + 3:6 * J + 6] = -skew(cJ)      # th_J x c^J = -c^J x th_J
+        D = E0 * (al * np.eye(3) + (1 - al) * np.outer(n, n))
+        K += s["facet_area"][k] / s["facet_len"][k] * B.T @ D @ B
+    Ko = _stiffness(orc)
+    assert np.abs(Ko - K).max() < 1e-11 * np.abs(K).max()
+
+
 def test_global_equilibrium_of_internal_forces():
     """Facet forces act in equal and opposite pairs on I and J with the
     moment arms of a common centroid, so the internal forces of any
