@@ -295,6 +295,18 @@ def test_autotune_keeps_the_trajectory():
     assert g.get_launch() == best
 
 
+def test_autotune_choice_is_cached_per_shape():
+    """A second system of the same shape (and precision) reuses the tuned
+    launch shape without new trials."""
+    s = tension_small()
+    g1 = gpu(s)
+    best1, _, trials1 = g1.autotune(steps_per_trial=10)
+    g2 = gpu(s)
+    best2, _, trials2 = g2.autotune(steps_per_trial=10)
+    assert len(trials2) == 0
+    assert best2 == best1 == g2.get_launch()
+
+
 def test_batched_uneven_specimens_against_oracle():
     """Three specimens of uneven size in one batched system: per-specimen
     energies and reactions from the GPU against the oracle run of each."""

@@ -125,3 +125,34 @@ def test_surrogate_end_to_end_accuracy_and_sticky_gate():
     assert counts[0] < F                         # the surrogate does carry facets
     assert abs(sg.max() - so.max()) <= 0.03 * abs(so.max())
     assert g.energy()["err"] <= 1e-2
+
+
+def test_surrogate_arguments_are_validated():
+    """Invalid surrogate descriptions are rejected with a status, not run."""
+    from paper_2603_13190_amd import surrogate as SG
+    from paper_2603_13190_amd.ldpm import LDPM_ERR_ARG, LDPM_ERR_STATE, LdpmError
+    s = tension_small()
+    p0 = SG.init_params(0)
+    args = (np.zeros(9), np.ones(9), np.ones(3), np.full(9, -1.0), np.full(9, 1.0))
+    g = gpu(s, precision="mixed")
+    for kw in (dict(y_dead=(-1.0, 0.0, 0.0)), dict(y_tau=-0.01), dict(y_dead=(np.nan, 0.0, 0.0))):
+        with pytest.raises(LdpmError) as ei:
+            g.set_surrogate(p0, *args, KT, KC, DMAX, **kw)
+        assert ei.value.status == LDPM_ERR_ARG, kw
+    bad = p0.copy()
+    bad[5] = np.inf
+    with pytest.raises(LdpmError) as ei:
+        g.set_surrogate(bad, *args, KT, KC, DMAX)
+    assert ei.value.status == LDPM_ERR_ARG
+    g64 = gpu(s, precision="fp64")
+    with pytest.raises(LdpmError) as ei:
+        g64.set_surrogate(p0, *args, KT, KC, DMAX)
+    assert ei.value.status == LDPM_ERR_STATE
+
+
+def test_capture_overflow_is_an_error():
+    """A capture that offers more rows than its capacity raises instead of
+    returning an arrival-order-dependent subset."""
+    from paper_2603_13190_amd import surrogate as SG
+    with pytest.raises(ValueError):
+        SG.capture(tension_small(), 50, facet_stride=1, step_stride=10, capacity=100)
