@@ -12,8 +12,13 @@
 
 namespace ldpm {
 
+// FP64: correctly rounded square root and division.  FP32 (the mixed path,
+// held to a stated tolerance, not to ulps): the hardware square root and
+// reciprocal, about 1 ulp each.
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ float d_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double d_div(double a, double b) { return a / b; }
+__device__ __forceinline__ float d_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double d_exp(double x) { return exp(x); }
 __device__ __forceinline__ float d_exp(float x) { return expf(x); }
 __device__ __forceinline__ double d_log(double x) { return log(x); }
@@ -100,22 +105,22 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
         // e^2 - e_old^2 = sum w_i de_i (e_i + e_old_i)
         const R num = de[0] * (eN + o0) + al * (de[1] * (eM + o1) + de[2] * (eL + o2));
         const R den = eff + effo;
-        const R deff = den > R(0) ? num / den : R(0);
+        const R deff = den > R(0) ? d_div(num, den) : R(0);
         const R teo = d_sqrt(t[0] * t[0] + (t[1] * t[1] + t[2] * t[2]) * p.inv_alpha);
-        const R inv = R(1) / seff;
+        const R inv = d_div(R(1), seff);
         const R sn = sN * inv;
         const R cs2 = al * sT2 * (inv * inv);
-        const R sigma0 = R(2) * p.sigma_t / (sn + d_sqrt(sn * sn + p.c4 * cs2));
+        const R sigma0 = d_div(R(2) * p.sigma_t, sn + d_sqrt(sn * sn + p.c4 * cs2));
         const R e0 = sigma0 * p.inv_E0;
         const R em = emax > eff ? emax : eff;
         const R over = em - e0;
         R sbt = sigma0;
         if (over > R(0)) {  // softening started: exp(-H0 <e_max - e0> / sigma0)
             const R omega = d_atan2(sN, d_sqrt(al * sT2));
-            const R Ht = R(2) * p.E0 / (p.l_t / len - R(1));
+            const R Ht = d_div(R(2) * p.E0, d_div(p.l_t, len) - R(1));
             // (2 omega / pi)^n_t for a base in [0, 1] (0 -> exp(-inf) = 0)
             const R H0 = p.Hs_over_alpha + (Ht - p.Hs_over_alpha) * d_exp(p.n_t * d_log(p.two_over_pi * omega));
-            sbt = sigma0 * d_exp(-H0 * over / sigma0);
+            sbt = sigma0 * d_exp(d_div(-H0 * over, sigma0));
         }
         const R etr = p.k_t * (em - sbt * p.inv_E0);
         R ttr;
@@ -143,14 +148,14 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
     R sbc = p.sigma_c0;
     if (-eDV > p.ec0) {  // beyond the onset of pore collapse
         const R aD = eD < R(0) ? -eD : eD;
-        const R rDV = (eV <= R(0)) ? -aD / (eV - p.eV0) : aD / p.eV0;
+        const R rDV = (eV <= R(0)) ? d_div(-aD, eV - p.eV0) : d_div(aD, p.eV0);
         const R xr = rDV - p.kc1;
-        const R Hc = (p.Hc0 - p.Hc1) / (R(1) + p.kc2 * (xr > R(0) ? xr : R(0))) + p.Hc1;
+        const R Hc = d_div(p.Hc0 - p.Hc1, R(1) + p.kc2 * (xr > R(0) ? xr : R(0))) + p.Hc1;
         if (-eDV <= p.ec1) {
             sbc = p.sigma_c0 + (-eDV - p.ec0) * Hc;
         } else {
             const R sc1 = p.sigma_c0 + (p.ec1 - p.ec0) * Hc;
-            sbc = sc1 * d_exp((-eDV - p.ec1) * Hc / sc1);
+            sbc = sc1 * d_exp(d_div((-eDV - p.ec1) * Hc, sc1));
         }
     }
     const R ENc = (-t[0] <= p.sigma_c0) ? p.E0 : p.Ed;
@@ -165,7 +170,7 @@ __device__ __forceinline__ void facet_law(const MatDev<R>& p, R len, const R e[3
         const R sbs = p.sigma_s + p.dmu_sN0 - p.mu_inf * tN - p.dmu_sN0 * d_exp(tN * p.inv_sigma_N0);
         const R nrm = d_sqrt(n2);
         if (nrm > sbs) {
-            const R f = sbs / nrm;
+            const R f = d_div(sbs, nrm);
             tM *= f;
             tL *= f;
         }
