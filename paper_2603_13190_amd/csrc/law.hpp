@@ -20,9 +20,11 @@ __device__ __forceinline__ float d_sqrt(float x) { return __builtin_amdgcn_sqrtf
 __device__ __forceinline__ double d_div(double a, double b) { return a / b; }
 __device__ __forceinline__ float d_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double d_exp(double x) { return exp(x); }
-__device__ __forceinline__ float d_exp(float x) { return expf(x); }
 __device__ __forceinline__ double d_log(double x) { return log(x); }
-__device__ __forceinline__ float d_log(float x) { return logf(x); }
+// FP32: exp x = 2^(x log2 e) and log x = log2(x) ln 2 on the transcendental
+// unit (a few ulp; overflow to +inf and log 0 = -inf are kept)
+__device__ __forceinline__ float d_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float d_log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 __device__ __forceinline__ double d_atan2(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float d_atan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double d_pow(double x, double y) { return pow(x, y); }
