@@ -656,17 +656,22 @@ __device__ __forceinline__ bool grid_barrier(const GridSync& g, unsigned nblocks
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();  // release this block's writes to the whole device
+        // release this block's writes to the device (one L2 write-back), read
+        // the generation, and only then arrive (the wait keeps the read ahead
+        // of the arrival, so the last arrival's increment cannot overtake it)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned gen0 = __hip_atomic_load(g.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived =
-            __hip_atomic_fetch_add(g.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        __builtin_amdgcn_s_waitcnt(0);
+        const unsigned arrived = __hip_atomic_fetch_add(g.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
         int ok = 1;
         if (arrived == nblocks) {
             __hip_atomic_store(g.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(g.gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
+            // poll with device-coherent relaxed loads (no cache maintenance per
+            // poll); bounded so that no wave can spin forever
             long spins = 0;
-            while (__hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
+            while (__hip_atomic_load(g.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > (1l << 24)) {  // ~seconds: never reached when co-resident
                     g.flag[1] = 1;
@@ -675,7 +680,8 @@ __device__ __forceinline__ bool grid_barrier(const GridSync& g, unsigned nblocks
                 }
             }
         }
-        __threadfence();  // acquire the other blocks' writes
+        // acquire the other blocks' writes (one L2 invalidation)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();
