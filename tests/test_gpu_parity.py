@@ -186,22 +186,23 @@ def test_resume_is_bitwise():
     assert st["step"] == 500
 
 
-def test_batched_equals_alone_bitwise():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_equals_alone_bitwise(precision):
     specs = [S.tension_cube(edge=e, d0=4.0, da=8.0, seed=i, rate=2.0, ramp=2e-4)
              for i, e in enumerate((20.0, 26.0, 23.0))]
     dt = min(x["dt"] for x in specs)
     batch = S.concat_specimens(specs, dt=dt)
-    gb = gpu(batch).step(300)
+    gb = gpu(batch, precision=precision).step(300)
     sb = gb.read_state()
     po, to = batch["particle_off"], batch["tet_off"]
     for i, sp in enumerate(specs):
         sp = dict(sp)
         sp["dt"] = dt
-        st = gpu(sp).step(300).read_state()
+        st = gpu(sp, precision=precision).step(300).read_state()
         assert np.array_equal(sb["q"][po[i]:po[i + 1]], st["q"])
         assert np.array_equal(sb["t"][12 * to[i]:12 * to[i + 1]], st["t"])
         eb = gb.energy(i)
-        ea = gpu(sp).step(300).energy()
+        ea = gpu(sp, precision=precision).step(300).energy()
         for k in ("W_int", "W_ext", "W_kin", "W_kin0"):
             assert eb[k] == ea[k], (i, k)
 

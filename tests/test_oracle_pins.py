@@ -475,6 +475,25 @@ def test_tension_reload_starts_at_e_tr():
     assert np.abs(t0 - np.minimum(p["E0"] * (again - elow), sbt)).max() < 1e-9 * p["sigma_t"]
 
 
+def test_branch_switches_are_continuous_for_elastic_states():
+    """Reading of the branch switch (history rebuilt from the stored vectors,
+    whichever branch produced them): on an elastic path that crosses e_N = 0
+    back and forth with shear, the tensile branch's effective-strain update
+    and the compressive branch's incremental update both stay on
+    t = E0 diag(1, alpha, alpha) e (appendix; elastic law)."""
+    p = dict(MB)
+    k = np.arange(1, 801)
+    path = np.zeros((k.size, 3))
+    path[:, 0] = 2e-5 * np.sin(k / 23.0)            # crosses zero many times
+    path[:, 1] = 1.5e-5 * np.sin(k / 37.0 + 0.4)
+    path[:, 2] = -1.0e-5 * np.cos(k / 29.0)
+    T, EM = O.drive_facet(p, 6.0, path)
+    E = p["E0"] * np.array([1.0, p["alpha"], p["alpha"]])
+    assert (path[:, 0] > 0).any() and (path[:, 0] < 0).any()
+    assert np.abs(T - E * path).max() < 1e-9 * np.abs(E * path).max()
+    assert EM.max() < 0.5 * p["sigma_t"] / p["E0"]   # stays below the elastic limit
+
+
 def test_hydrostatic_compression_closed_form():
     """e_N = e_V = -e (e_D = 0, r_DV = 0 so H_c = H_c0): elastic to -sigma_c0
     at e_c0 = sigma_c0/E0, then linear hardening sigma_c0 + (e - e_c0) H_c0 up
