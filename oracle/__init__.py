@@ -6,7 +6,10 @@ CPU-baseline leg of the benchmark, never by the solver package.
 Parity unpinned (no external reference exists for these; they follow the
 documented readings, and the GPU path is compared against them): the
 tessellation details, the history reset at branch switches, the e_max rule,
-and whole trajectories of the inelastic workloads.
+whole trajectories of the inelastic workloads, and the reading that the
+facet law takes a random perturbation's jump as an increment of its own
+(its invariants are pinned: masking, rigid jumps, elastic work, consistency
+of history and positions, energy balance).
 """
 from __future__ import annotations
 
@@ -47,7 +50,7 @@ class OraSys(C.Structure):
 class OraState(C.Structure):
     _fields_ = [("q", _dp), ("v", _dp), ("t", _dp), ("e", _dp), ("emax", _dp), ("fext", _dp),
                 ("W_int", C.c_double), ("W_ext", C.c_double), ("W_kin", C.c_double),
-                ("W_kin0", C.c_double), ("step", C.c_int64)]
+                ("W_kin0", C.c_double), ("W_pert", C.c_double), ("step", C.c_int64)]
 
 
 def lib():
@@ -69,6 +72,8 @@ def lib():
         L.ora_all_strains.argtypes = [C.POINTER(OraSys), _dp, _dp]
         L.ora_all_volstrains.argtypes = [C.POINTER(OraSys), _dp, _dp]
         L.ora_max_threads.restype = C.c_int
+        L.ora_perturb.argtypes = [C.POINTER(OraSys), C.POINTER(OraState), _dp]
+        L.ora_perturb.restype = C.c_double
         _lib = L
     return _lib
 
@@ -141,7 +146,7 @@ class Oracle:
     def step_index(self):
         return int(self.st.step)
 
-    def set_state(self, q, v, t, e, emax, fext, step, W=(0.0, 0.0, 0.0, 0.0)):
+    def set_state(self, q, v, t, e, emax, fext, step, W=(0.0, 0.0, 0.0, 0.0), W_pert=0.0):
         self.q[...] = q
         self.v[...] = v
         self.t[...] = t
@@ -150,11 +155,13 @@ class Oracle:
         self.fext[...] = fext
         self.st.step = int(step)
         self.st.W_int, self.st.W_ext, self.st.W_kin, self.st.W_kin0 = map(float, W)
+        self.st.W_pert = float(W_pert)
 
     def energies(self):
         s = self.st
-        return dict(W_int=s.W_int, W_ext=s.W_ext, W_kin=s.W_kin, W_kin0=s.W_kin0,
-                    step=int(s.step), err=energy_error(s.W_ext, s.W_int, s.W_kin, s.W_kin0))
+        return dict(W_int=s.W_int, W_ext=s.W_ext, W_kin=s.W_kin, W_kin0=s.W_kin0, W_pert=s.W_pert,
+                    step=int(s.step),
+                    err=energy_error(s.W_ext, s.W_int, s.W_kin, s.W_kin0, W_pert=s.W_pert))
 
     def step(self, n=1):
         rc = lib().ora_step(C.byref(self.sys), C.byref(self.st), int(n), int(self.nthreads))
@@ -181,16 +188,96 @@ class Oracle:
         lib().ora_elastic_internal_force(C.byref(self.sys), _ptr(q, _dp), _ptr(f, _dp))
         return f
 
+    def perturb(self, delta):
+        """Add delta (N, 6) to the free DoFs; the facet law takes the jump as
+        an increment of its own (see ora_perturb).  Returns its work."""
+        d = np.ascontiguousarray(delta, dtype=np.float64)
+        if d.shape != (self.N, 6):
+            raise ValueError("delta must have shape (N, 6)")
+        return float(lib().ora_perturb(C.byref(self.sys), C.byref(self.st), _ptr(d, _dp)))
+
+    def last_configuration(self):
+        """q^{n-1} = q^n - dt v^{n-1/2}, the configuration at which the facet
+        history was last evaluated (the undeformed one before the first step)."""
+        if self.step_index == 0:
+            return np.zeros_like(self.q)
+        return self.q - float(self.sys.dt) * self.v
+
+    def crack_opening(self):
+        """Per-facet crack-opening vector and its magnitude, (F, 4):
+        w_N, w_M, w_L, |w| (see crack_opening)."""
+        md = self.sys.mat
+        return crack_opening(self.e, self.t, self.arr["len"], md.E0, md.alpha)
+
+    def volumetric_strain_field(self):
+        """e_V of every tetrahedron at the configuration of the last law
+        evaluation (zero before the first step)."""
+        if self.step_index == 0:
+            return np.zeros(self.T)
+        return self.volstrains(self.last_configuration())
+
     def reaction_sum(self, prog_id):
         sel = self.arr["dof_prog"] == prog_id
         return float(self.fext[sel].sum())
 
 
-def energy_error(W_ext, W_int, W_kin, W_kin0, tiny=1e-300):
-    """|W_ext + W_kin0 - W_int - W_kin| / max(|W_ext + W_kin0|, tiny); with
-    W_kin0 = 0 this is the paper's energy-balance measure divided by 100."""
-    den = max(abs(W_ext + W_kin0), tiny)
-    return abs(W_ext + W_kin0 - W_int - W_kin) / den
+def energy_error(W_ext, W_int, W_kin, W_kin0, tiny=1e-300, W_pert=0.0):
+    """|W_ext + W_pert + W_kin0 - W_int - W_kin| / max(|W_ext + W_pert + W_kin0|, tiny);
+    with W_kin0 = W_pert = 0 this is the paper's energy-balance measure
+    divided by 100.  W_pert is the work of random perturbations, done on the
+    specimen from outside like W_ext."""
+    src = W_ext + W_pert + W_kin0
+    den = max(abs(src), tiny)
+    return abs(src - W_int - W_kin) / den
+
+
+def crack_opening(e, t, length, E0, alpha):
+    """Crack opening of each facet (numerical-examples section, comparison
+    of crack patterns): the inelastic part of the facet strain times the
+    facet length, w_a = l (e_a - t_a / E_a) with E = E0 diag(1, alpha, alpha),
+    where only a positive (opening) inelastic normal strain counts,
+    w_N = max(w_N, 0); total opening |w| = sqrt(w_N^2 + w_M^2 + w_L^2).
+    e, t: (F, 3) strain and traction of the same law evaluation; returns
+    (F, 4) = w_N, w_M, w_L, |w|."""
+    e = np.asarray(e, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    L = np.asarray(length, dtype=np.float64)
+    Ed = np.array([E0, alpha * E0, alpha * E0])
+    w = L[:, None] * (e - t / Ed)
+    w[:, 0] = np.maximum(w[:, 0], 0.0)
+    out = np.empty((w.shape[0], 4))
+    out[:, :3] = w
+    out[:, 3] = np.sqrt(w[:, 0] ** 2 + w[:, 1] ** 2 + w[:, 2] ** 2)
+    return out
+
+
+def field_stats(x, ref, cap=None):
+    """Pairwise comparison of two per-facet (or per-tetrahedron) fields as
+    the paper compares crack patterns (numerical-examples section): Pearson's
+    correlation coefficient and NRMSE = 100 / w~ * sqrt(mean (x - ref)^2),
+    with w~ the maximum of the reference field.  cap (optional): both fields
+    are limited to it first (the paper limits crack openings to 4 mm in the
+    unconfined compression comparisons).  Definitions written out in FP64,
+    two passes (means, then centred sums)."""
+    x = np.asarray(x, dtype=np.float64).ravel()
+    r = np.asarray(ref, dtype=np.float64).ravel()
+    if x.shape != r.shape or x.size == 0:
+        raise ValueError("fields must have the same, non-zero size")
+    if cap is not None and cap > 0 and np.isfinite(cap):
+        x = np.minimum(x, cap)
+        r = np.minimum(r, cap)
+    n = x.size
+    mx = x.sum() / n
+    mr = r.sum() / n
+    dx = x - mx
+    dr = r - mr
+    with np.errstate(divide="ignore", invalid="ignore"):
+        pearson = float((dx * dr).sum() / np.sqrt((dx * dx).sum() * (dr * dr).sum()))
+        rmse = float(np.sqrt(((x - r) ** 2).sum() / n))
+        ref_max = float(r.max())
+        nrmse = float(np.float64(100.0) * rmse / np.float64(ref_max))
+    return dict(n=n, mean_x=float(mx), mean_ref=float(mr), pearson=pearson, rmse=rmse,
+                ref_max=ref_max, nrmse=nrmse)
 
 
 def facet_law(mat, length, e, e_old, eV, t_old, emax_old):

@@ -78,6 +78,7 @@ typedef struct {
     double *emax;        /* [F] */
     double *fext;        /* [N][6]: applied + reaction generalised force of the last step */
     double W_int, W_ext, W_kin, W_kin0;
+    double W_pert;       /* work of the random perturbations (ora_perturb) */
     int64_t step;        /* completed steps */
 } ora_state;
 
@@ -431,6 +432,59 @@ void ora_elastic_internal_force(const ora_sys *s, const double *q, double *fint)
             fJ[3 + i] += MJ[i];
         }
     }
+}
+
+/* Random perturbation of the solution (section on the numerical study of
+ * time step, convergence criteria and stability): delta [N][6] is added to
+ * every free DoF (displacements and rotations) of every particle; prescribed
+ * DoFs keep their values.
+ * Reading (the paper does not say how the facet history sees the jump): the
+ * jump is a strain increment of its own, taken by the facet law at once.
+ * It starts from the configuration of the last law evaluation,
+ * q^{n-1} = q^n - dt v^{n-1/2}, whose strain is the stored e, and ends at that
+ * configuration plus the jump; so the next step starts from a history that
+ * matches the perturbed positions.  The traction work of the jump
+ * (trapezoid, as for a step) is added to W_int and, being done on the
+ * specimen from outside, to W_pert.  Before the first step there is no
+ * history yet: the jump only changes the initial displacement.
+ * Returns the work of this jump.                                           */
+double ora_perturb(const ora_sys *s, ora_state *st, const double *delta)
+{
+    const int64_t N = s->N, T = s->T, F = s->F;
+    double *d = (double *)malloc(sizeof(double) * 6 * (size_t)(N > 0 ? N : 1));
+    for (int64_t id = 0; id < 6 * N; id++) d[id] = s->dof_mode[id] == 0 ? delta[id] : 0.0;
+    double W = 0.0;
+    if (st->step > 0) {
+        double *qj = (double *)malloc(sizeof(double) * 6 * (size_t)(N > 0 ? N : 1));
+        double *eV = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+        double *dW = (double *)malloc(sizeof(double) * (size_t)(F > 0 ? F : 1));
+        for (int64_t id = 0; id < 6 * N; id++) qj[id] = st->q[id] - s->dt * st->v[id] + d[id];
+        tet_volstrains(s, qj, eV);
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < F; k++) {
+            double de[3], e[3], t[3], em;
+            ora_facet_strain(d + 6 * (int64_t)s->fI[k], d + 6 * (int64_t)s->fJ[k], s->cI + 3 * k,
+                             s->n + 3 * k, s->m + 3 * k, s->len[k], de);
+            for (int i = 0; i < 3; i++) e[i] = st->e[3 * k + i] + de[i];
+            ora_facet_law(&s->mat, s->len[k], e, st->e + 3 * k, eV[s->ftet[k]], st->t + 3 * k,
+                          st->emax[k], t, &em);
+            double w = 0.0;
+            for (int i = 0; i < 3; i++) w += 0.5 * (st->t[3 * k + i] + t[i]) * de[i];
+            dW[k] = s->A[k] * s->len[k] * w;
+            for (int i = 0; i < 3; i++) {
+                st->e[3 * k + i] = e[i];
+                st->t[3 * k + i] = t[i];
+            }
+            st->emax[k] = em;
+        }
+        for (int64_t k = 0; k < F; k++) W += dW[k];
+        st->W_int += W;
+        st->W_pert += W;
+        free(qj); free(eV); free(dW);
+    }
+    for (int64_t id = 0; id < 6 * N; id++) st->q[id] += d[id];
+    free(d);
+    return W;
 }
 
 /* All facet strains for a given q (test helper). */

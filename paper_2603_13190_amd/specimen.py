@@ -961,3 +961,15 @@ def cylinder_cycle(D=100.0, H=200.0, d0=2.0, da=4.0, seed=1, eps_t=1.2e-4, eps_c
                     dict(d0=d0, da=da, seed=seed, lam_max=float(lam.max()), height=H,
                          area=np.pi * D * D / 4, load_prog=pid, total_time=float(t),
                          n_steps=int(np.ceil(t / dt))))
+
+
+def perturbation(n_particles, eta, seed, index):
+    """Random jump of every DoF (displacements and rotations) of n_particles
+    particles, uniform in [-eta/2, eta/2], shape (N, 6): the random vector of
+    the paper's perturbation study (section on time step, convergence
+    criteria and stability).  Draw `index` of the sequence `seed`; the solver
+    applies it to the free DoFs only."""
+    if not eta >= 0.0:
+        raise ValueError("eta must be non-negative")
+    rng = np.random.default_rng([int(seed), int(index)])
+    return rng.uniform(-0.5 * eta, 0.5 * eta, size=(int(n_particles), 6))
