@@ -171,6 +171,129 @@ def batched_case(args, tune):
     return rec
 
 
+def paper_class(st):
+    """The paper's four agreement classes for a (Pearson, NRMSE) pair
+    (numerical-examples section; the correlation bound of the first class is
+    read as > 0.999)."""
+    r, e = st["pearson"], st["nrmse"]
+    if r > 0.999 and e < 1.0:
+        return "practically identical"
+    if r > 0.9 and e < 5.0:
+        return "minor differences"
+    if r > 0.8 and e < 10.0:
+        return "major differences"
+    return "largely different"
+
+
+def field_stats(x, ref, cap=None):
+    from paper_2603_13190_amd.ldpm import compare_fields
+    st = compare_fields(x, ref, cap=cap)
+    st["class"] = paper_class(st)
+    return st
+
+
+def crack_kernel_bytes(info):
+    """Compulsory HBM bytes of one crack-opening launch: per facet the record
+    id (4 B), c^I and t (6 R) and the written w (4 doubles); per edge frame
+    8 R; per tetrahedron the two node ids the facets use (16 B); per
+    particle q and v (12 doubles)."""
+    rb = 4.0 if info["precision"] == 1 else 8.0
+    return (info["n_facets"] * (4.0 + 6.0 * rb + 32.0) + info["n_edges"] * 8.0 * rb + info["n_tets"] * 16.0
+            + info["n_particles"] * 96.0)
+
+
+def time_on_stream(fn, reps):
+    """Average GPU time (ms) of fn() over reps calls, torch events on the
+    current stream (the library's stream)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def kernel_rates(g, w, ref):
+    """Crack-opening kernel and field-comparison kernels: GB/s against HBM."""
+    info = g.info()
+    out = {}
+    ms = time_on_stream(lambda: g.crack_opening(out=w), 20)
+    bts = crack_kernel_bytes(info)
+    out["crack_kernel"] = {"avg_us": ms * 1e3, "alg_bytes": bts, "GBs": bts / (ms * 1e-3) / 1e9,
+                           "frac_hbm": bts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    from paper_2603_13190_amd.ldpm import compare_fields
+    x = w[3]
+    ms = time_on_stream(lambda: compare_fields(x, ref), 10)
+    bts = 16.0 * x.numel()
+    out["compare_fields"] = {"avg_us": ms * 1e3, "alg_bytes": bts, "GBs": bts / (ms * 1e-3) / 1e9,
+                             "frac_hbm": bts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                             "note": "two kernels plus a 56 B copy to the host and the stream wait"}
+    return out
+
+
+def perturbed_run(sysd, eta, interval, total, every, seed):
+    """The tension trajectory with a random jump U(-eta/2, eta/2) of every
+    free DoF each `interval` steps; nominal stress every `every` steps."""
+    from paper_2603_13190_amd import specimen as S
+    from paper_2603_13190_amd.ldpm import System
+    g = System(sysd, precision="fp64")
+    prog, area = sysd["meta"]["load_prog"], sysd["meta"]["area"]
+    N = sysd["meta"]["N"]
+    hist, done, k, work = [], 0, 0, 0.0
+    while done < total:
+        n = min(every - done % every, interval - done % interval, total - done)
+        g.step(n)
+        done += n
+        if done % interval == 0 and done < total:
+            work += g.perturb(S.perturbation(N, eta, seed=seed, index=k))
+            k += 1
+        if done % every == 0 or done == total:
+            hist.append(g.reaction(prog) / area)
+    return hist, g.energy(), g, k
+
+
+def crack_case(sysd, g64, gmx, h64, total):
+    """Crack patterns at the end of the tension trajectory: mixed vs FP64, and
+    the perturbation study (jumps every 0.002 s, two eta) vs the unperturbed
+    FP64 run; kernel rates of the crack-opening and comparison kernels."""
+    every = max(1, total // 100)
+    w64 = g64.crack_opening().clone()
+    wmx = gmx.crack_opening().clone()
+    rec = {"cracked_facets_fp64": int((w64[3] > 1e-3).sum().item()),
+           "max_opening_mm_fp64": float(w64[3].max().item())}
+    rec["mixed_vs_fp64"] = field_stats(wmx[3].contiguous(), w64[3].contiguous())
+    log(f"crack pattern mixed vs fp64: pearson {rec['mixed_vs_fp64']['pearson']:.6f}, "
+        f"nrmse {rec['mixed_vs_fp64']['nrmse']:.3e} % ({rec['mixed_vs_fp64']['class']})")
+    interval = max(1, int(round(0.002 / sysd["dt"])))
+    pk64 = max(h64)
+    study = {"interval_steps": interval, "interval_s": interval * sysd["dt"],
+             "note": "random jump of every free displacement and rotation, uniform in [-eta/2, eta/2] "
+                     "(mm, rad); the facet law takes each jump as an increment of its own"}
+    for eta in (1e-5, 1e-4):
+        h, en, gp, njump = perturbed_run(sysd, eta, interval, total, every, seed=7)
+        wp = gp.crack_opening()
+        st = field_stats(wp[3].contiguous(), w64[3].contiguous())
+        ha = np.array(h)
+        study[f"eta_{eta:g}"] = {
+            "jumps": njump, "peak_stress_MPa": float(ha.max()),
+            "peak_stress_rel_diff": float(abs(ha.max() - pk64) / abs(pk64)),
+            "stress_history_max_rel_diff": float(np.abs(ha - np.array(h64)).max() / abs(pk64)),
+            "W_pert_over_W_int": en["W_pert"] / en["W_int"], "energy_balance_err": en["err"],
+            "crack_vs_unperturbed": st}
+        gp.close()
+        log(f"perturbation eta {eta:g}: {njump} jumps, peak {ha.max():.4f} MPa (unperturbed {pk64:.4f}), "
+            f"crack pearson {st['pearson']:.4f}, nrmse {st['nrmse']:.2f} % ({st['class']}), "
+            f"energy err {en['err']:.2e}")
+    rec["perturbation_study"] = study
+    rec["kernels"] = kernel_rates(g64, w64, w64[3].contiguous())
+    return rec
+
+
 def cycle_run(sysd, precision, model=None, every=1000, launch=None):
     """Whole cyclic trajectory; nominal stress history, energy error, timing
     (reaction sampling outside the timed spans), surrogate share."""
@@ -265,16 +388,19 @@ def surrogate_case(args, sysd_tension, tune):
     return rec, model
 
 
-def window_case(sysd, workload, runs, warmup, steps, tune):
+def window_case(sysd, workload, runs, warmup, steps, tune, field=None):
     """Throughput of `steps` explicit steps after `warmup` steps from the
     initial state, per precision (and with the surrogate when a model is
-    given), with the facet kernel's HBM rate from HIP-event kernel times."""
+    given), with the facet kernel's HBM rate from HIP-event kernel times.
+    field ("crack" or "volumetric"): the runs' end fields are compared
+    pairwise as the paper compares solutions (Pearson, NRMSE)."""
     import torch
     from paper_2603_13190_amd.ldpm import System
     m = sysd["meta"]
     F = m["F"]
     rec = {"workload": workload, "particles": m["N"], "tets": m["T"], "facets": F, "dt": sysd["dt"],
            "warmup": warmup, "steps": steps, "generation_s": m.get("generation_s")}
+    fields = {}
     for name, prec, model in runs:
         g = System(sysd, precision=prec)
         r = {}
@@ -303,11 +429,28 @@ def window_case(sysd, workload, runs, warmup, steps, tune):
                      facet_kernel_frac_hbm=info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9 / PEAK_HBM_GBS)
         else:
             r["surrogate_share_of_facets_at_end"] = 1.0 - g.surrogate_count() / F
+        if field == "crack":
+            w = g.crack_opening()
+            fields[name] = w[3].clone()
+            if name == "fp64":
+                r["field_kernels"] = kernel_rates(g, w, fields[name])
+        elif field == "volumetric":
+            fields[name] = g.volumetric_strain().clone()
         g.close()
         rec[name] = r
         extra = f", facet kernel {r['facet_kernel_GBs']:.0f} GB/s" if "facet_kernel_GBs" in r else \
             f", surrogate share at end {r['surrogate_share_of_facets_at_end']:.3f}"
         log(f"{workload.split(',')[0]} {name}: {r['value']:.4e} facet-upd/s{extra}")
+    if field and "fp64" in fields:
+        cmp_ = {}
+        for name in fields:
+            if name != "fp64":
+                cmp_[f"{name}_vs_fp64"] = field_stats(fields[name], fields["fp64"])
+        if "surrogate" in fields and "mixed_exact" in fields:
+            cmp_["surrogate_vs_mixed_exact"] = field_stats(fields["surrogate"], fields["mixed_exact"])
+        rec[f"{field}_field_comparison"] = cmp_
+        for k, v in cmp_.items():
+            log(f"{workload.split(',')[0]} {field} field {k}: pearson {v['pearson']:.6f}, nrmse {v['nrmse']:.3e} %")
     return rec
 
 
@@ -336,6 +479,8 @@ def main():
     ap.add_argument("--cyl-full-d0", type=float, default=1.1)
     ap.add_argument("--large-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-crack", action="store_true",
+                    help="skip the crack-pattern comparison and the perturbation study")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="bytes of a plain device copy to run (counter calibration)")
     args = ap.parse_args()
@@ -422,8 +567,7 @@ def main():
     # ---- accuracy: nominal stress histories, FP64 vs mixed ----
     if not args.no_accuracy and "load_prog" in sysd["meta"]:
         every = max(1, (args.warmup + steps) // 100)
-        h64, e64, g = accuracy_run(sysd, "fp64", args.warmup + steps, every, launch)
-        g.close()
+        h64, e64, gacc64 = accuracy_run(sysd, "fp64", args.warmup + steps, every, launch)
         peak64 = max(h64)
         out["peak_stress_fp64_MPa"] = peak64
         out["quasi_static"] = {"kin_over_int_max_after_ramp": e64["kin_over_int_max_after_ramp"],
@@ -431,8 +575,7 @@ def main():
         log(f"quasi-static: W_kin/W_int max after the ramp {e64['kin_over_int_max_after_ramp']:.2e}, "
             f"at the end {e64['kin_over_int_end']:.2e}")
         if not args.no_mixed:
-            hmx, emx, g = accuracy_run(sysd, "mixed", args.warmup + steps, every, launch)
-            g.close()
+            hmx, emx, gaccmx = accuracy_run(sysd, "mixed", args.warmup + steps, every, launch)
             peakmx = max(hmx)
             h64a, hmxa = np.array(h64), np.array(hmx)
             out["mixed"].update({
@@ -452,6 +595,17 @@ def main():
             log(f"{name}: failed: {exc!r}")
             out[name] = {"error": repr(exc)}
             return None
+
+    # ---- crack patterns and the perturbation study (tension trajectory) ----
+    if not args.no_accuracy and not args.no_mixed and "load_prog" in sysd["meta"]:
+        if not args.no_crack:
+            r = optional("crack", lambda: crack_case(sysd, gacc64, gaccmx, h64, args.warmup + steps))
+            if r is not None:
+                out["crack"] = r
+        gacc64.close()
+        gaccmx.close()
+    elif not args.no_accuracy and "load_prog" in sysd["meta"]:
+        gacc64.close()
 
     # ---- batched: 64 uneven specimens in one system (window of steps) ----
     if not args.no_batch:
@@ -473,7 +627,7 @@ def main():
             return window_case(
                 conf, "confined compression, 150 mm cube, d 4-12 mm, seed 1, 20 MPa lateral pressure "
                       "then axial shortening", [("fp64", "fp64", None), ("mixed", "mixed", None)],
-                2000, args.large_steps, tune)
+                2000, args.large_steps, tune, field="volumetric")
 
         def cylinder():
             cyl = futs["cylinder"].result()
@@ -482,7 +636,7 @@ def main():
                 runs.append(("surrogate", "mixed", model))
             return window_case(
                 cyl, f"cylinder 100 x 200 mm, d {args.cyl_full_d0:g}-{2 * args.cyl_full_d0:g} mm, seed 1, "
-                     "window in the first tension leg", runs, 3000, args.large_steps, tune)
+                     "window in the first tension leg", runs, 3000, args.large_steps, tune, field="crack")
         for name, fn in (("confined150", confined), ("cylinder_full", cylinder)):
             r = optional(name, fn)
             if r is not None:

@@ -103,6 +103,7 @@ typedef struct {
     double *w_ext;      /* [N]    accumulated external work per particle     */
     double *w_kin;      /* [N]    kinetic energy per particle at the last step */
     double *w_kin0;     /* [n_specimens] initial kinetic energy              */
+    double *w_pert;     /* [n_specimens] work of random perturbations (ldpm_perturb) */
     int64_t step;       /* completed steps n                                 */
 } ldpm_state;
 
@@ -156,7 +157,8 @@ typedef struct {
     double W_int;   /* work of the facet tractions (trapezoid per facet) */
     double W_kin;   /* kinetic energy at step n-1, mid-step velocities averaged */
     double W_kin0;  /* initial kinetic energy */
-    double err;     /* |W_ext + W_kin0 - W_int - W_kin| / max(|W_ext + W_kin0|, tiny) */
+    double W_pert;  /* work of random perturbations (ldpm_perturb), done from outside */
+    double err;     /* |W_src - W_int - W_kin| / max(|W_src|, tiny), W_src = W_ext + W_pert + W_kin0 */
     int64_t step;
     double time;    /* t_{n-1} */
 } ldpm_energies;
@@ -318,6 +320,68 @@ ldpm_status ldpm_capture_begin(ldpm_system *s, const ldpm_capture_opts *opts);
 /* Ends the capture; *n_rows = rows offered (may exceed the capacity);
  * copies min(n_rows, capacity, max_rows) rows into host rows[][16].      */
 ldpm_status ldpm_capture_end(ldpm_system *s, float *rows, int64_t max_rows, int64_t *n_rows);
+
+/* ---- Crack openings, volumetric strains, field comparison ----------------
+ * The paper compares two solutions of a benchmark by their final crack
+ * patterns (and, for confined compression, volumetric strains) through
+ * Pearson's correlation coefficient and an NRMSE (numerical-examples
+ * section).  The fields are written to DEVICE memory (on the handle's GPU),
+ * enqueued on the handle's stream; a host pointer is rejected
+ * (LDPM_ERR_ARG).                                                          */
+
+/* Crack-opening vector of every facet after the last completed step n,
+ * w [4][F] doubles: w_N, w_M, w_L, |w|, with w = len_k (e - E^{-1} t),
+ * E = E0 diag(1, alpha, alpha), e and t the strain and traction of the last
+ * law evaluation (configuration q^{n-1} = q^n - dt v^{n-1/2}; before the
+ * first step the undeformed one), and only a positive normal inelastic
+ * strain opening a crack: w_N = max(w_N, 0).                               */
+ldpm_status ldpm_crack_opening(ldpm_system *s, double *w);
+
+/* Volumetric strain e_V of every tetrahedron at the configuration of the
+ * last law evaluation (zero before the first step), ev [T] doubles.        */
+ldpm_status ldpm_volumetric_strain(ldpm_system *s, double *ev);
+
+/* Comparison of a field x with a reference field ref (n doubles each, in
+ * DEVICE memory of the current GPU): Pearson's correlation coefficient and
+ * NRMSE = 100 / max(ref) * sqrt(mean (x - ref)^2), in percent.  cap > 0 and
+ * finite: both fields are limited to cap first (the paper limits crack
+ * openings to 4 mm where detached fragments would dominate); otherwise no
+ * limit.  The reduction order depends on n only (bitwise reproducible).
+ * IEEE results for degenerate fields: pearson is NaN when either field is
+ * constant, nrmse is inf or NaN when max(ref) is 0.  Runs on `stream`
+ * (hipStream_t or NULL), allocates a small temporary device buffer and
+ * synchronises the stream.                                                 */
+typedef struct {
+    int64_t n;
+    double mean_x, mean_ref;
+    double pearson;
+    double rmse;     /* sqrt(mean (x - ref)^2) */
+    double ref_max;  /* max ref (after the cap): the normalisation */
+    double nrmse;    /* percent */
+} ldpm_field_stats;
+ldpm_status ldpm_compare_fields(const double *x, const double *ref, int64_t n, double cap, void *stream,
+                                ldpm_field_stats *out);
+
+/* ---- Random perturbation of the solution ---------------------------------
+ * The paper tests the stability of a strain-softening response by adding,
+ * at regular intervals, a random vector uniform in [-eta/2, eta/2] to all
+ * free displacements and rotations (section on the numerical study of time
+ * step, convergence criteria and stability).  ldpm_perturb adds delta (HOST
+ * memory [6][N], copied; the caller draws it) to every free DoF of q^n;
+ * prescribed DoFs keep their values, velocities are unchanged.  The facet
+ * law takes the jump as a strain increment of its own, at once: from the
+ * configuration of the last law evaluation (q^{n-1} = q^n - dt v^{n-1/2}) to
+ * that configuration plus the jump, so that the next step starts from a
+ * history consistent with the perturbed positions (the paper does not say
+ * how the history sees the jump; this is the reading taken).  The
+ * traction work of the jump is added to the internal work and, as work done
+ * from outside, to W_pert of each specimen.  Before the first step there is
+ * no history: the jump only changes the initial displacement.  With a
+ * surrogate installed the jump still goes through the exact law, and a
+ * capture records nothing for it.  *work (may be NULL) receives the work of
+ * this jump over all specimens.  Synchronises the stream.  The first call
+ * allocates a device buffer of about 8 (6N + 2T) bytes, kept by the handle. */
+ldpm_status ldpm_perturb(ldpm_system *s, const double *delta, double *work);
 
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);

@@ -82,6 +82,7 @@ ldpm_status ldpm_fail(ldpm_status st, const char* fmt, ...)
     } while (0)
 
 #include "step_kernels.hpp"
+#include "fields.hpp"
 
 // ---------------------------------------------------------------------------
 // host side
@@ -119,6 +120,10 @@ struct ldpm_system {
     CaptureArgs cp{};
     void* sg_mem = nullptr;  // params + flags
     void* cp_mem = nullptr;  // rows + counter
+    // random perturbations: work per specimen, device staging (jump [6][N],
+    // e_V [T], jump work [T], per-specimen sums)
+    std::vector<double> wpert;
+    void* pt_mem = nullptr;
 };
 
 namespace {
@@ -690,6 +695,9 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
             s->wkin0[sp] = w;
         }
     }
+    s->wpert.assign(nspec, 0.0);
+    if (is && is->w_pert)
+        for (int i = 0; i < nspec; i++) s->wpert[i] = is->w_pert[i];
     s->step = is ? is->step : 0;
     if (s->step < 0) { ldpm_free(s); return fail(LDPM_ERR_ARG, "negative step in init_state"); }
     e = hipStreamSynchronize(s->stream);
@@ -772,6 +780,7 @@ ldpm_status ldpm_read_state(ldpm_system* s, ldpm_state* o)
     if (o->w_ext) HIP_TRY(hipMemcpy(o->w_ext, s->wext, N * 8, hipMemcpyDeviceToHost));
     if (o->w_kin) HIP_TRY(hipMemcpy(o->w_kin, s->wkin, N * 8, hipMemcpyDeviceToHost));
     if (o->w_kin0) for (int i = 0; i < s->nspec; i++) o->w_kin0[i] = s->wkin0[i];
+    if (o->w_pert) for (int i = 0; i < s->nspec; i++) o->w_pert[i] = s->wpert[i];
     auto get_r = [&](double* dst, const void* src, size_t n) -> hipError_t {
         if (s->prec == LDPM_PREC_MIXED) {
             std::vector<float> tmp(n);
@@ -802,8 +811,9 @@ ldpm_status ldpm_energy(ldpm_system* s, int32_t sp, ldpm_energies* o)
     o->W_ext = r[1];
     o->W_kin = s->step > 0 ? r[2] : s->wkin0[sp];
     o->W_kin0 = s->wkin0[sp];
-    const double den = std::max(std::fabs(o->W_ext + o->W_kin0), 1e-300);
-    o->err = std::fabs(o->W_ext + o->W_kin0 - o->W_int - o->W_kin) / den;
+    o->W_pert = s->wpert[sp];
+    const double src = o->W_ext + o->W_pert + o->W_kin0;
+    o->err = std::fabs(src - o->W_int - o->W_kin) / std::max(std::fabs(src), 1e-300);
     o->step = s->step;
     o->time = (double)(s->step > 0 ? s->step - 1 : 0) * s->dt;
     return st;
@@ -869,6 +879,7 @@ ldpm_status ldpm_set_launch(ldpm_system* s, const ldpm_launch* c)
 // and results do not depend on the launch shape, so tuning never changes the
 // trajectory.  Choices are cached per (GPU architecture, system shape).
 // ---------------------------------------------------------------------------
+extern "C++" {
 namespace {
 struct TuneKey {
     std::string arch;
@@ -900,6 +911,7 @@ std::vector<Region> dynamic_regions(ldpm_system* s)
             {s->wkin, N * 8},  {s->wint, T * 8},    {s->ht, 3 * F * rb},  {s->hemax, F * rb}};
 }
 }  // namespace
+}  // extern "C++"
 
 ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* best, double* best_us,
                           ldpm_tune_trial* trials, int32_t max_trials, int32_t* n_trials)
@@ -1103,6 +1115,156 @@ ldpm_status ldpm_capture_end(ldpm_system* s, float* rows, int64_t max_rows, int6
     return LDPM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// crack openings, volumetric strains, field comparison, random perturbation
+// ---------------------------------------------------------------------------
+extern "C++" {
+namespace {
+// is p device memory of the given device?  (clears the error a host pointer
+// leaves behind)
+bool on_device(const void* p, int device)
+{
+    hipPointerAttribute_t a;
+    const hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == device;
+}
+
+unsigned blocks_for(int64_t n, int th) { return (unsigned)((n + th - 1) / th); }
+
+template <typename R>
+FacetArgs<R> facet_args(ldpm_system* s)
+{
+    return FacetArgs<R>{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->frame, (R*)s->ht, (R*)s->hemax,
+                        s->F, s->E};
+}
+}  // namespace
+}  // extern "C++"
+
+ldpm_status ldpm_crack_opening(ldpm_system* s, double* w)
+{
+    if (!s || !w) return fail(LDPM_ERR_ARG, "null argument");
+    if (!on_device(w, s->device)) return fail(LDPM_ERR_ARG, "crack_opening: w must be device memory of the handle's GPU");
+    NodeArgs na{s->tet, s->node, s->N, s->T};
+    const double E0 = s->matd.E0, aE0 = s->matd.aE0;
+    const int first = s->step == 0;
+    if (s->prec == LDPM_PREC_MIXED)
+        hipLaunchKernelGGL(k_crack<float>, dim3(blocks_for(s->F, 256)), dim3(256), 0, s->stream, na,
+                           facet_args<float>(s), E0, aE0, s->dt, first, w);
+    else
+        hipLaunchKernelGGL(k_crack<double>, dim3(blocks_for(s->F, 256)), dim3(256), 0, s->stream, na,
+                           facet_args<double>(s), E0, aE0, s->dt, first, w);
+    HIP_TRY(hipGetLastError());
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_volumetric_strain(ldpm_system* s, double* ev)
+{
+    if (!s || !ev) return fail(LDPM_ERR_ARG, "null argument");
+    if (!on_device(ev, s->device))
+        return fail(LDPM_ERR_ARG, "volumetric_strain: ev must be device memory of the handle's GPU");
+    NodeArgs na{s->tet, s->node, s->N, s->T};
+    hipLaunchKernelGGL(k_volstrain, dim3(blocks_for(s->T, 256)), dim3(256), 0, s->stream, na, s->dt,
+                       (int)(s->step == 0), (const double*)nullptr, ev);
+    HIP_TRY(hipGetLastError());
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_compare_fields(const double* x, const double* ref, int64_t n, double cap, void* stream,
+                                ldpm_field_stats* out)
+{
+    if (!x || !ref || !out) return fail(LDPM_ERR_ARG, "null argument");
+    if (n <= 0) return fail(LDPM_ERR_ARG, "compare_fields: n must be positive");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (!on_device(x, dev) || !on_device(ref, dev))
+        return fail(LDPM_ERR_ARG, "compare_fields: x and ref must be device memory of the current GPU");
+    hipStream_t st = (hipStream_t)stream;
+    const int G = (int)std::min<int64_t>(CMP_MAX_BLOCKS, (n + CMP_THREADS - 1) / CMP_THREADS);
+    void* mem = nullptr;
+    const size_t bytes = (size_t)G * sizeof(Moments) + 8 * sizeof(double);
+    if (hipMalloc(&mem, bytes) != hipSuccess) return fail(LDPM_ERR_ALLOC, "compare_fields: hipMalloc(%zu) failed", bytes);
+    Moments* part = (Moments*)mem;
+    double* res = (double*)((char*)mem + (size_t)G * sizeof(Moments));
+    const int use_cap = (cap > 0.0 && std::isfinite(cap)) ? 1 : 0;
+    hipLaunchKernelGGL(k_cmp_partial, dim3(G), dim3(CMP_THREADS), 0, st, x, ref, n, cap, use_cap, part);
+    hipLaunchKernelGGL(k_cmp_final, dim3(1), dim3(CMP_THREADS), 0, st, (const Moments*)part, G, res);
+    hipError_t e = hipGetLastError();
+    double r[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "compare_fields failed: %s", hipGetErrorString(e));
+    out->n = (int64_t)r[0];
+    out->mean_x = r[1];
+    out->mean_ref = r[2];
+    out->pearson = r[3];
+    out->rmse = r[4];
+    out->ref_max = r[5];
+    out->nrmse = r[6];
+    return LDPM_OK;
+}
+
+extern "C++" template <typename R, int LAW>
+static void launch_jump(ldpm_system* s, const double* d, const double* evj, double* wj)
+{
+    NodeArgs na{s->tet, s->node, s->N, s->T};
+    const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
+    hipLaunchKernelGGL((k_jump<R, LAW>), dim3(blocks_for(s->T, 256)), dim3(256), 0, s->stream, na, facet_args<R>(s),
+                       mat, d, evj, s->dt, s->wint, wj);
+}
+
+ldpm_status ldpm_perturb(ldpm_system* s, const double* delta, double* work)
+{
+    if (!s || !delta) return fail(LDPM_ERR_ARG, "null argument");
+    const int64_t N = s->N, T = s->T;
+    if (!finite_all(delta, 6 * N)) return fail(LDPM_ERR_ARG, "perturb: non-finite delta");
+    Carve cv;
+    const size_t o_d = cv.take<double>(6 * N), o_ev = cv.take<double>(T), o_wj = cv.take<double>(T);
+    const size_t o_sum = cv.take<double>(s->nspec);
+    const size_t bytes = (cv.off + 255) & ~size_t(255);
+    if (!s->pt_mem && hipMalloc(&s->pt_mem, bytes) != hipSuccess) {
+        s->pt_mem = nullptr;
+        return fail(LDPM_ERR_ALLOC, "perturb: hipMalloc(%zu) failed", bytes);
+    }
+    char* B = (char*)s->pt_mem;
+    double *d = (double*)(B + o_d), *evj = (double*)(B + o_ev), *wj = (double*)(B + o_wj);
+    double* sums = (double*)(B + o_sum);
+    HIP_TRY(hipMemcpyAsync(d, delta, 6 * N * 8, hipMemcpyHostToDevice, s->stream));
+    hipLaunchKernelGGL(k_mask_free, dim3(blocks_for(6 * N, 256)), dim3(256), 0, s->stream, s->mode, 6 * N, d);
+    std::vector<double> w(s->nspec, 0.0);
+    if (s->step > 0) {
+        NodeArgs na{s->tet, s->node, s->N, s->T};
+        hipLaunchKernelGGL(k_volstrain, dim3(blocks_for(T, 256)), dim3(256), 0, s->stream, na, s->dt, 0,
+                           (const double*)d, evj);
+        if (s->prec == LDPM_PREC_MIXED) {
+            if (s->law == 0) launch_jump<float, 0>(s, d, evj, wj);
+            else launch_jump<float, 1>(s, d, evj, wj);
+        } else {
+            if (s->law == 0) launch_jump<double, 0>(s, d, evj, wj);
+            else launch_jump<double, 1>(s, d, evj, wj);
+        }
+        for (int sp = 0; sp < s->nspec; sp++)
+            hipLaunchKernelGGL(k_range_sum, dim3(1), dim3(RED_THREADS), 0, s->stream, (const double*)wj, s->toff[sp],
+                               s->toff[sp + 1], sums + sp);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(w.data(), sums, s->nspec * 8, hipMemcpyDeviceToHost, s->stream));
+    }
+    hipLaunchKernelGGL(k_add_jump, dim3(blocks_for(6 * N, 256)), dim3(256), 0, s->stream, s->node, (const double*)d, N);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    for (int sp = 0; sp < s->nspec; sp++) {
+        s->wpert[sp] += w[sp];
+        tot += w[sp];
+    }
+    if (work) *work = tot;
+    return LDPM_OK;
+}
+
 ldpm_status ldpm_get_launch(ldpm_system* s, ldpm_launch* o)
 {
     if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
@@ -1116,6 +1278,7 @@ void ldpm_free(ldpm_system* s)
     (void)hipStreamSynchronize(s->stream);
     if (s->sg_mem) (void)hipFree(s->sg_mem);
     if (s->cp_mem) (void)hipFree(s->cp_mem);
+    if (s->pt_mem) (void)hipFree(s->pt_mem);
     if (s->arena) {
         (void)hipStreamSynchronize(s->stream);
         if (s->dev_free) s->dev_free(s->arena, s->alloc_ctx);

@@ -25,7 +25,8 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_free", "ldpm_mlp_num_params", "ldpm_mlp_create", "ldpm_mlp_set_data",
            "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
            "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_capture_begin",
-           "ldpm_capture_end",
+           "ldpm_capture_end", "ldpm_crack_opening", "ldpm_volumetric_strain", "ldpm_compare_fields",
+           "ldpm_perturb",
            "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
@@ -46,7 +47,7 @@ class Material(C.Structure):
 class State(C.Structure):
     _fields_ = [("q", _dp), ("v", _dp), ("t", _dp), ("emax", _dp), ("fext", _dp),
                 ("w_int", _dp), ("w_ext", _dp), ("w_kin", _dp), ("w_kin0", _dp),
-                ("step", C.c_int64)]
+                ("w_pert", _dp), ("step", C.c_int64)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -70,8 +71,8 @@ class SystemDesc(C.Structure):
 
 class Energies(C.Structure):
     _fields_ = [("W_ext", C.c_double), ("W_int", C.c_double), ("W_kin", C.c_double),
-                ("W_kin0", C.c_double), ("err", C.c_double), ("step", C.c_int64),
-                ("time", C.c_double)]
+                ("W_kin0", C.c_double), ("W_pert", C.c_double), ("err", C.c_double),
+                ("step", C.c_int64), ("time", C.c_double)]
 
 
 class Info(C.Structure):
@@ -102,6 +103,12 @@ class CaptureOpts(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("facet_stride", C.c_int32), ("facet_offset", C.c_int32),
                 ("step_stride", C.c_int32), ("kappa_t", C.c_float), ("kappa_c", C.c_float),
                 ("damage_max", C.c_float)]
+
+
+class FieldStats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean_x", C.c_double), ("mean_ref", C.c_double),
+                ("pearson", C.c_double), ("rmse", C.c_double), ("ref_max", C.c_double),
+                ("nrmse", C.c_double)]
 
 
 class LdpmError(RuntimeError):
@@ -149,6 +156,11 @@ def lib():
         L.ldpm_surrogate_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.ldpm_capture_begin.argtypes = [C.c_void_p, C.POINTER(CaptureOpts)]
         L.ldpm_capture_end.argtypes = [C.c_void_p, _fp, C.c_int64, C.POINTER(C.c_int64)]
+        L.ldpm_crack_opening.argtypes = [C.c_void_p, C.c_void_p]
+        L.ldpm_volumetric_strain.argtypes = [C.c_void_p, C.c_void_p]
+        L.ldpm_compare_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
+                                          C.POINTER(FieldStats)]
+        L.ldpm_perturb.argtypes = [C.c_void_p, _dp, _dp]
         L.ldpm_free.argtypes = [C.c_void_p]
         L.ldpm_free.restype = None
         L.ldpm_last_error.restype = C.c_char_p
@@ -324,7 +336,7 @@ class System:
     def _state_struct(self, state=None, fill=False):
         N, T, F = self.N, self.T, self.F
         shapes = dict(q=(6, N), v=(6, N), t=(3, F), emax=(F,), fext=(6, N), w_int=(T,),
-                      w_ext=(N,), w_kin=(N,), w_kin0=(self.nspec,))
+                      w_ext=(N,), w_kin=(N,), w_kin0=(self.nspec,), w_pert=(self.nspec,))
         arrs = {}
         st = State()
         for name, shp in shapes.items():
@@ -365,8 +377,8 @@ class System:
     def energy(self, specimen=0):
         e = Energies()
         _check(lib().ldpm_energy(self.h, int(specimen), C.byref(e)))
-        return dict(W_ext=e.W_ext, W_int=e.W_int, W_kin=e.W_kin, W_kin0=e.W_kin0, err=e.err,
-                    step=int(e.step), time=e.time)
+        return dict(W_ext=e.W_ext, W_int=e.W_int, W_kin=e.W_kin, W_kin0=e.W_kin0, W_pert=e.W_pert,
+                    err=e.err, step=int(e.step), time=e.time)
 
     def reaction(self, program):
         out = C.c_double()
@@ -448,6 +460,36 @@ class System:
         return dict(x=rows[:, :9].copy(), y=rows[:, 9:12].copy(), s=rows[:, 14].copy(), step=key >> 32,
                     facet=key & 0xffffffff, offered=int(n.value))
 
+    def crack_opening(self, out=None):
+        """Crack-opening vectors after the last step: device tensor (4, F)
+        = w_N, w_M, w_L, |w| (enqueued on the handle's stream)."""
+        import torch
+        if out is None:
+            out = torch.empty((4, self.F), dtype=torch.float64, device="cuda")
+        _check_out(out, (4, self.F))
+        _check(lib().ldpm_crack_opening(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def volumetric_strain(self, out=None):
+        """e_V per tetrahedron at the last evaluated configuration: device tensor (T,)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.T,), dtype=torch.float64, device="cuda")
+        _check_out(out, (self.T,))
+        _check(lib().ldpm_volumetric_strain(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def perturb(self, delta):
+        """Add delta (N, 6) (generator layout) to the free DoFs; returns the
+        work of the jump."""
+        d = np.asarray(delta, dtype=np.float64)
+        if d.shape != (self.N, 6):
+            raise ValueError("delta must have shape (N, 6)")
+        d = np.ascontiguousarray(d.T)
+        w = C.c_double()
+        _check(lib().ldpm_perturb(self.h, _p(d, _dp), C.byref(w)))
+        return float(w.value)
+
     def close(self):
         if getattr(self, "h", None):
             lib().ldpm_free(self.h)
@@ -458,6 +500,30 @@ class System:
             self.close()
         except Exception:  # noqa: BLE001
             pass
+
+
+def _check_out(t, shape):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
+        raise ValueError(f"output must be a contiguous float64 device tensor of shape {shape}")
+
+
+def compare_fields(x, ref, cap=None, stream=None):
+    """Pearson's correlation and NRMSE (percent, normalised by max ref) of
+    two device tensors of the same size (float64), optionally limited to cap
+    first.  Returns a dict."""
+    import torch
+    for t in (x, ref):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("fields must be contiguous float64 device tensors")
+    if x.numel() != ref.numel():
+        raise ValueError("fields must have the same size")
+    st = torch.cuda.current_stream() if stream is None else stream
+    o = FieldStats()
+    _check(lib().ldpm_compare_fields(C.c_void_p(x.data_ptr()), C.c_void_p(ref.data_ptr()), int(x.numel()),
+                                     float(cap) if cap is not None else 0.0, C.c_void_p(st.cuda_stream),
+                                     C.byref(o)))
+    return {f: getattr(o, f) for f, _ in FieldStats._fields_}
 
 
 class Mlp:
@@ -503,6 +569,36 @@ class Mlp:
         p = np.zeros(self.n_params, dtype=np.float32)
         _check(lib().ldpm_mlp_get_params(self.h, p.ctypes.data_as(_fp)))
         return p
+
+    def crack_opening(self, out=None):
+        """Crack-opening vectors after the last step: device tensor (4, F)
+        = w_N, w_M, w_L, |w| (enqueued on the handle's stream)."""
+        import torch
+        if out is None:
+            out = torch.empty((4, self.F), dtype=torch.float64, device="cuda")
+        _check_out(out, (4, self.F))
+        _check(lib().ldpm_crack_opening(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def volumetric_strain(self, out=None):
+        """e_V per tetrahedron at the last evaluated configuration: device tensor (T,)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.T,), dtype=torch.float64, device="cuda")
+        _check_out(out, (self.T,))
+        _check(lib().ldpm_volumetric_strain(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def perturb(self, delta):
+        """Add delta (N, 6) (generator layout) to the free DoFs; returns the
+        work of the jump."""
+        d = np.asarray(delta, dtype=np.float64)
+        if d.shape != (self.N, 6):
+            raise ValueError("delta must have shape (N, 6)")
+        d = np.ascontiguousarray(d.T)
+        w = C.c_double()
+        _check(lib().ldpm_perturb(self.h, _p(d, _dp), C.byref(w)))
+        return float(w.value)
 
     def close(self):
         if getattr(self, "h", None):

@@ -973,3 +973,31 @@ def perturbation(n_particles, eta, seed, index):
         raise ValueError("eta must be non-negative")
     rng = np.random.default_rng([int(seed), int(index)])
     return rng.uniform(-0.5 * eta, 0.5 * eta, size=(int(n_particles), 6))
+
+
+def synthetic_state(sysd, seed, strain, noise=0.3, t_normal=(-60.0, 4.0), t_shear=3.0,
+                    emax_max=4e-4, step=1000):
+    """A seeded, loaded state with facet history, for checks at full size that
+    cannot afford a trajectory on the CPU: translations u = strain . x0 plus
+    noise (relative amplitude `noise` of the strain times 4 mm, rotations
+    likewise per mm), random mid-step velocities whose step increment dt v is
+    about a tenth of the noise, facet tractions drawn uniformly (normal in
+    t_normal, each shear component in +-t_shear, MPa) and e_max uniformly in
+    [0, emax_max], independently of the strains.  Returns a dict with q, v
+    (N, 6), t (F, 3), emax (F,), fext (N, 6) zero, and step."""
+    rng = np.random.default_rng(seed)
+    x = np.asarray(sysd["x0"], dtype=np.float64)
+    N = x.shape[0]
+    F = int(np.asarray(sysd["facet_I"]).shape[0])
+    eps = np.asarray(strain, dtype=np.float64).reshape(3, 3)
+    amp = noise * float(np.abs(eps).max()) * 4.0
+    q = np.zeros((N, 6))
+    q[:, :3] = x @ eps.T + amp * rng.standard_normal((N, 3))
+    q[:, 3:] = 0.5 * (eps - eps.T)[[2, 0, 1], [1, 2, 0]] + (amp / 4.0) * rng.standard_normal((N, 3))
+    v = (0.1 * amp / float(sysd["dt"])) * rng.standard_normal((N, 6))
+    v[:, 3:] /= 4.0
+    t = np.empty((F, 3))
+    t[:, 0] = rng.uniform(t_normal[0], t_normal[1], F)
+    t[:, 1:] = rng.uniform(-t_shear, t_shear, (F, 2))
+    emax = rng.uniform(0.0, emax_max, F)
+    return dict(q=q, v=v, t=t, emax=emax, fext=np.zeros((N, 6)), step=int(step))

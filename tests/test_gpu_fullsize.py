@@ -36,19 +36,22 @@ def test_elastic_cube50_whole_trajectory():
     assert eg["err"] < 1e-3
 
 
-def test_confined_cube150_one_step_from_late_state():
-    """150 mm confined compression (648k facets): one step from a GPU state
-    deep in the loading (pressure applied, axial compression under way),
-    against the oracle started from the same state."""
+def test_confined_cube150_one_step_from_a_seeded_loaded_state():
+    """150 mm confined compression (648k facets): one step from a seeded
+    loaded state (compressive strain field with noise, velocities, facet
+    history, drawn by the input generator), on both sides."""
+    from paper_2603_13190_amd import specimen as S
     s = confined_full()
-    g = gpu(s).step(60000)
-    st = g.read_state()
+    st = S.synthetic_state(s, seed=5, strain=np.diag([-2e-3, -2e-3, -6e-3]), t_normal=(-150.0, 0.0),
+                           t_shear=20.0, step=60000)
     o = O.Oracle(s)
     e_old = o.strains(st["q"] - s["dt"] * st["v"])     # q^{n-1} = q^n - dt v^{n-1/2}
     o.set_state(st["q"], st["v"], st["t"], e_old, st["emax"], st["fext"], st["step"])
-    assert (st["t"][:, 0] < -1.0).sum() > 1000          # compressive facets present
+    g = gpu(s, init_state=st)
     o.step(1)
     g.step(1)
+    assert (o.t[:, 0] < -1.0).sum() > 100000            # compressive facets
+    assert (o.e[:, 0] < -s["material"]["sigma_c0"] / s["material"]["E0"]).sum() > 1000   # beyond pore collapse
     st2 = g.read_state()
     for f in ("q", "v", "t", "emax", "fext"):
         assert rel(st2[f], getattr(o, f)) <= 1e-10, f
