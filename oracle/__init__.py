@@ -44,7 +44,7 @@ class OraSys(C.Structure):
                 ("cI", _dp), ("n", _dp), ("m", _dp), ("A", _dp), ("len", _dp),
                 ("dof_mode", _up), ("dof_prog", _ip), ("dof_scale", _dp),
                 ("n_prog", C.c_int64), ("prog_off", _lp), ("prog_t", _dp), ("prog_v", _dp),
-                ("body", _dp), ("dt", C.c_double), ("mat", OraMat)]
+                ("body", _dp), ("dt", C.c_double), ("mat", OraMat), ("mass_block", _dp)]
 
 
 class OraState(C.Structure):
@@ -123,6 +123,11 @@ class Oracle:
         s.prog_off = _ptr(a["prog_off"], _lp)
         s.dt = float(sysd["dt"])
         s.mat = make_mat(sysd["material"])
+        if sysd.get("mass_block") is not None:
+            a["mass_block"] = np.ascontiguousarray(sysd["mass_block"], dtype=np.float64)
+            if a["mass_block"].shape != (s.N, 21):
+                raise ValueError("mass_block must have shape (N, 21)")
+            s.mass_block = _ptr(a["mass_block"], _dp)
         self.sys = s
         self.N, self.T, self.F = int(s.N), int(s.T), int(s.F)
         self.nthreads = nthreads

@@ -70,6 +70,11 @@ typedef struct {
     const double *body;      /* [3] body force per unit volume */
     double dt;
     ora_mat mat;
+    /* [N][21] or NULL: full rigid-body mass block of each cell about its
+     * particle centre (eq. balance: M_u, M_theta, I_u, I_theta), upper
+     * triangle row-major over (u_x, u_y, u_z, th_x, th_y, th_z); NULL: the
+     * lumped diagonal (mass, inertia) */
+    const double *mass_block;
 } ora_sys;
 
 typedef struct {
@@ -292,8 +297,75 @@ static void tet_volstrains(const ora_sys *s, const double *q, double *eV)
     }
 }
 
+/* Solve A x = b for the n x n leading part of A (row stride 6) by Gaussian
+ * elimination with partial pivoting; A and b are overwritten.             */
+static void solve_small(double A[6][6], double *b, double *x, int n)
+{
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        for (int r = c + 1; r < n; r++)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < n; k++) {
+                double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t;
+            }
+            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < n; r++) {
+            double f = A[r][c] / A[c][c];
+            for (int k = c; k < n; k++) A[r][k] -= f * A[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; r--) {
+        double acc = b[r];
+        for (int k = r + 1; k < n; k++) acc -= A[r][k] * x[k];
+        x[r] = acc / A[r][r];
+    }
+}
+
+/* Velocity update of one particle with a full 6 x 6 mass block Mb (eq. of
+ * motion M q'' = f_ext - f_int restricted to the particle): prescribed DoFs
+ * take their programmed velocity, whose acceleration a_P = (v+ - v-)/h
+ * enters the free rows: M_FF a_F = fnet_F - M_FP a_P; the reactions are
+ * R_P = M_PF a_F + M_PP a_P - fnet_P.                                      */
+static void block_update(const double Mb[6][6], const int pres[6], const double fnet[6], const double vold[6],
+                         const double vpres[6], double h, double vnew[6], double react[6])
+{
+    double a[6], A[6][6], r[6], x[6];
+    int fi[6], nf = 0;
+    for (int d = 0; d < 6; d++) {
+        if (pres[d]) {
+            vnew[d] = vpres[d];
+            a[d] = (vnew[d] - vold[d]) / h;
+        } else {
+            fi[nf++] = d;
+        }
+    }
+    for (int i = 0; i < nf; i++) {
+        r[i] = fnet[fi[i]];
+        for (int k = 0; k < 6; k++)
+            if (pres[k]) r[i] -= Mb[fi[i]][k] * a[k];
+        for (int j = 0; j < nf; j++) A[i][j] = Mb[fi[i]][fi[j]];
+    }
+    if (nf > 0) solve_small(A, r, x, nf);
+    for (int i = 0; i < nf; i++) {
+        a[fi[i]] = x[i];
+        vnew[fi[i]] = vold[fi[i]] + h * x[i];
+    }
+    for (int d = 0; d < 6; d++) {
+        react[d] = 0.0;
+        if (pres[d]) {
+            double ma = 0.0;
+            for (int k = 0; k < 6; k++) ma += Mb[d][k] * a[k];
+            react[d] = ma - fnet[d];
+        }
+    }
+}
+
 /* Explicit central-difference steps (eq. of motion M q'' + f_int = f_ext with
- * lumped M).  Returns 0, or 1 if a non-finite value appeared.             */
+ * the lumped diagonal M, or the full per-cell blocks).  Returns 0, or 1 if a
+ * non-finite value appeared.                                                */
 int ora_step(const ora_sys *s, ora_state *st, int64_t nsteps, int nthreads)
 {
 #ifdef _OPENMP
@@ -369,6 +441,39 @@ int ora_step(const ora_sys *s, ora_state *st, int64_t nsteps, int nthreads)
                     body[i] = s->cell_vol[I] * s->body[i];
                     body[3 + i] = s->cell_vol[I] * rxb[i];
                 }
+            }
+            if (s->mass_block) {
+                double Mb[6][6], fnet[6], applied[6], vold[6], vpres[6], vnew[6], react[6];
+                int pres[6];
+                const double *ut = s->mass_block + 21 * I;
+                for (int r = 0, k = 0; r < 6; r++)
+                    for (int c = r; c < 6; c++, k++) Mb[r][c] = Mb[c][r] = ut[k];
+                for (int d = 0; d < 6; d++) {
+                    const int64_t id = 6 * I + d;
+                    const int32_t pg = s->dof_prog[id];
+                    applied[d] = body[d];
+                    if (s->dof_mode[id] == 0 && pg >= 0) applied[d] += s->dof_scale[id] * prog_eval(s, pg, time);
+                    fnet[d] = f[id] + applied[d];
+                    vold[d] = st->v[id];
+                    pres[d] = s->dof_mode[id] != 0;
+                    vpres[d] = (pres[d] && pg >= 0) ? s->dof_scale[id] * prog_eval(s, pg, t_half) : 0.0;
+                }
+                block_update(Mb, pres, fnet, vold, vpres, h, vnew, react);
+                double vbar[6];
+                for (int d = 0; d < 6; d++) vbar[d] = (n == 0) ? vold[d] : 0.5 * (vold[d] + vnew[d]);
+                for (int d = 0; d < 6; d++) {
+                    const int64_t id = 6 * I + d;
+                    const double Fd = applied[d] + react[d];
+                    if (n > 0) dWext += 0.5 * (st->fext[id] + Fd) * (dt * vold[d]);
+                    double Mvb = 0.0;
+                    for (int k = 0; k < 6; k++) Mvb += Mb[d][k] * vbar[k];
+                    Wk += 0.5 * vbar[d] * Mvb;
+                    st->fext[id] = Fd;
+                    st->v[id] = vnew[d];
+                    st->q[id] += dt * vnew[d];
+                    if (!isfinite(vnew[d])) bad = 1;
+                }
+                continue;
             }
             for (int d = 0; d < 6; d++) {
                 const int64_t id = 6 * I + d;

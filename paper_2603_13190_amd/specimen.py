@@ -417,8 +417,9 @@ def tessellate(x, diam, tets):
 
 
 def cell_mass_properties(x, tets, tri, rho):
-    """Mass, diagonal rotational inertia about the centre, cell volume and
-    centroid offset of every polyhedral cell (exact cone sums)."""
+    """Mass, diagonal rotational inertia about the centre, cell volume,
+    centroid offset and full inertia tensor (about the centre) of every
+    polyhedral cell (exact cone sums)."""
     N = x.shape[0]
     P0, P1, P2, avec, I, J = tri["P0"], tri["P1"], tri["P2"], tri["avec"], tri["I"], tri["J"]
     vol = np.zeros(N)
@@ -447,7 +448,8 @@ def cell_mass_properties(x, tets, tri, rho):
     tr = np.trace(mom2, axis1=1, axis2=2)
     inertia = rho * (tr[:, None] - np.einsum("nii->ni", mom2))
     r_off = mom1 / np.maximum(vol, 1e-300)[:, None]
-    return mass, inertia, vol, r_off
+    J = rho * (tr[:, None, None] * np.eye(3)[None] - mom2)
+    return mass, inertia, vol, r_off, J
 
 
 def element_mass_share(x, tets, tri, rho):
@@ -485,32 +487,32 @@ def _skew(c):
                      np.stack([-c[..., 1], c[..., 0], z], -1)], -2)
 
 
-def element_lambda_max(sysd, E0, alpha, chunk=8192, workers=None):
-    """Largest eigenvalue of each tetrahedron's elastic operator with its
-    share of the lumped mass; the max over tetrahedra bounds the assembled
-    system's largest eigenvalue from above.
+class _TetStiffness:
+    """Elastic stiffness of tetrahedra s0..s1 (t, 24, 24), DoFs ordered
+    (local node, u_x, u_y, u_z, th_x, th_y, th_z).
 
     Facet k couples the 6-DoF blocks of its nodes I and J through
     B = [-1, S(c^I) | 1, -S(c^J)] (jump = B q) and D = E0 (alpha 1 + (1 - alpha) n n^T):
-    K_tet = sum_k (A_k / l_k) B^T D B.  Chunks run on a thread pool (the
-    batched products and eigvalsh release the GIL)."""
-    from concurrent.futures import ThreadPoolExecutor
-    tets = sysd["tet_nodes"].astype(np.int64)
-    T = tets.shape[0]
-    mshare = sysd["_elem_mass"]
-    lam = np.empty(T)
-    fI = sysd["facet_I"].reshape(T, 12)
-    ga = tets[:, FACET_LOCAL[:, 0]]
-    locI = np.where(fI == ga, FACET_LOCAL[None, :, 0], FACET_LOCAL[None, :, 1])
-    locJ = np.where(fI == ga, FACET_LOCAL[None, :, 1], FACET_LOCAL[None, :, 0])
-    cI = sysd["facet_cI"].reshape(T, 12, 3)
-    n = sysd["facet_n"].reshape(T, 12, 3)
-    ln = sysd["facet_len"].reshape(T, 12)
-    A = sysd["facet_area"].reshape(T, 12)
-    eye3 = np.eye(3)
+    K_tet = sum_k (A_k / l_k) B^T D B."""
 
-    def one(s0):
-        s1 = min(T, s0 + chunk)
+    def __init__(self, sysd, E0, alpha):
+        tets = sysd["tet_nodes"].astype(np.int64)
+        T = tets.shape[0]
+        self.T = T
+        fI = sysd["facet_I"].reshape(T, 12)
+        ga = tets[:, FACET_LOCAL[:, 0]]
+        self.locI = np.where(fI == ga, FACET_LOCAL[None, :, 0], FACET_LOCAL[None, :, 1])
+        self.locJ = np.where(fI == ga, FACET_LOCAL[None, :, 1], FACET_LOCAL[None, :, 0])
+        self.cI = sysd["facet_cI"].reshape(T, 12, 3)
+        self.n = sysd["facet_n"].reshape(T, 12, 3)
+        self.ln = sysd["facet_len"].reshape(T, 12)
+        self.A = sysd["facet_area"].reshape(T, 12)
+        self.E0, self.alpha = E0, alpha
+
+    def __call__(self, s0, s1):
+        E0, alpha = self.E0, self.alpha
+        cI, n, ln, A, locI, locJ = self.cI, self.n, self.ln, self.A, self.locI, self.locJ
+        eye3 = np.eye(3)
         t = s1 - s0
         rows = np.arange(t)
         K = np.zeros((t, 4, 6, 4, 6))
@@ -528,7 +530,24 @@ def element_lambda_max(sysd, E0, alpha, chunk=8192, workers=None):
             K[rows, li, :, lj, :] += GIt @ DJ
             K[rows, lj, :, li, :] += GJt @ DI
             K[rows, lj, :, lj, :] += GJt @ DJ
-        K = K.reshape(t, 24, 24)
+        return K.reshape(t, 24, 24)
+
+
+def element_lambda_max(sysd, E0, alpha, chunk=8192, workers=None):
+    """Largest eigenvalue of each tetrahedron's elastic operator with its
+    share of the lumped mass; the max over tetrahedra bounds the assembled
+    system's largest eigenvalue from above.  Chunks run on a thread pool
+    (the batched products and eigvalsh release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    ks = _TetStiffness(sysd, E0, alpha)
+    T = ks.T
+    mshare = sysd["_elem_mass"]
+    lam = np.empty(T)
+
+    def one(s0):
+        s1 = min(T, s0 + chunk)
+        t = s1 - s0
+        K = ks(s0, s1)
         wgt = 1.0 / np.sqrt(mshare[s0:s1].reshape(t, 24))
         Kh = K * wgt[:, :, None] * wgt[:, None, :]
         lam[s0:s1] = np.linalg.eigvalsh(Kh)[:, -1]
@@ -538,6 +557,53 @@ def element_lambda_max(sysd, E0, alpha, chunk=8192, workers=None):
     with ThreadPoolExecutor(max_workers=nw) as ex:
         list(ex.map(one, starts))
     return lam
+
+
+def global_stiffness(sysd, chunk=8192):
+    """Assembled elastic stiffness (6N x 6N, scipy CSR) from the
+    tetrahedra's matrices; used to compare stable steps across mass
+    representations."""
+    import scipy.sparse as sp
+    mat = sysd["material"]
+    ks = _TetStiffness(sysd, mat["E0"], mat["alpha"])
+    tets = sysd["tet_nodes"].astype(np.int64)
+    N = sysd["x0"].shape[0]
+    rows, cols, vals = [], [], []
+    for s0 in range(0, ks.T, chunk):
+        s1 = min(ks.T, s0 + chunk)
+        K = ks(s0, s1)
+        dof = (6 * tets[s0:s1, :, None] + np.arange(6)[None, None, :]).reshape(-1, 24)
+        rows.append(np.repeat(dof[:, :, None], 24, axis=2).ravel())
+        cols.append(np.repeat(dof[:, None, :], 24, axis=1).ravel())
+        vals.append(K.ravel())
+    K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(6 * N, 6 * N)).tocsr()
+    return 0.5 * (K + K.T)
+
+
+def mass_matrix(sysd):
+    """Assembled mass (6N x 6N, scipy CSR): the per-cell blocks of
+    `mass_block` when present, else the diagonal (mass, inertia)."""
+    import scipy.sparse as sp
+    N = sysd["x0"].shape[0]
+    if sysd.get("mass_block") is not None:
+        iu = np.triu_indices(6)
+        B = np.zeros((N, 6, 6))
+        B[:, iu[0], iu[1]] = sysd["mass_block"]
+        B[:, iu[1], iu[0]] = sysd["mass_block"]
+        return sp.block_diag(list(B), format="csr")
+    d = np.empty((N, 6))
+    d[:, :3] = np.asarray(sysd["mass"])[:, None]
+    d[:, 3:] = sysd["inertia"]
+    return sp.diags(d.ravel()).tocsr()
+
+
+def lambda_max(sysd):
+    """Largest eigenvalue of K phi = lambda M phi of the assembled system."""
+    import scipy.sparse.linalg as sla
+    K = global_stiffness(sysd)
+    M = mass_matrix(sysd)
+    return float(sla.eigsh(K, k=1, M=M, which="LA", tol=1e-9, return_eigenvectors=False)[0])
 
 
 def boundary_triangles(tets):
@@ -582,9 +648,9 @@ def build_geometry(shape: Shape, d0, da, seed, gap=0.1, rho=RHO, vol_fraction=No
     cen = x[tets].mean(axis=1)
     tets = tets[np.argsort(_morton_keys(cen), kind="stable")]
     fac, tri = tessellate(x, diam, tets)
-    mass, inertia, cvol, roff = cell_mass_properties(x, tets, tri, rho)
+    mass, inertia, cvol, roff, cJ = cell_mass_properties(x, tets, tri, rho)
     sysd = dict(x0=x, diam=diam, is_surface=is_surf, tet_nodes=tets.astype(np.int32),
-                mass=mass, inertia=inertia, cell_vol=cvol, cell_r=roff, **fac)
+                mass=mass, inertia=inertia, cell_vol=cvol, cell_r=roff, cell_inertia=cJ, **fac)
     sysd["_elem_mass"] = element_mass_share(x, tets, tri, rho)
     sysd["_tri"] = tri
     return sysd
@@ -799,6 +865,9 @@ def concat_specimens(specs: List[dict], dt=None):
               "facet_cI", "facet_n", "facet_m", "facet_area", "facet_len", "facet_area0",
               "dof_mode", "dof_scale", "v0", "q0"):
         out[k] = cat(k)
+    for k in ("cell_inertia", "mass_block"):
+        if all(k in s for s in specs):
+            out[k] = cat(k)
     out["tet_nodes"] = np.concatenate([s["tet_nodes"] + N_off[i] for i, s in enumerate(specs)]).astype(np.int32)
     out["facet_I"] = np.concatenate([s["facet_I"] + N_off[i] for i, s in enumerate(specs)]).astype(np.int32)
     out["facet_J"] = np.concatenate([s["facet_J"] + N_off[i] for i, s in enumerate(specs)]).astype(np.int32)
@@ -856,10 +925,10 @@ def system_from_points(x, diam, tets=None, mat=None, rho=RHO, dt=None, name="poi
         neg = v6 < 0
         tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
     fac, tri = tessellate(x, diam, tets)
-    mass, inertia, cvol, roff = cell_mass_properties(x, tets, tri, rho)
+    mass, inertia, cvol, roff, cJ = cell_mass_properties(x, tets, tri, rho)
     g = dict(x0=x, diam=diam, is_surface=np.zeros(x.shape[0], bool),
              tet_nodes=tets.astype(np.int32), mass=mass, inertia=inertia, cell_vol=cvol,
-             cell_r=roff, **fac)
+             cell_r=roff, cell_inertia=cJ, **fac)
     g["_elem_mass"] = element_mass_share(x, tets, tri, rho)
     N = x.shape[0]
     if dt is None:
@@ -1001,3 +1070,74 @@ def synthetic_state(sysd, seed, strain, noise=0.3, t_normal=(-60.0, 4.0), t_shea
     t[:, 1:] = rng.uniform(-t_shear, t_shear, (F, 2))
     emax = rng.uniform(0.0, emax_max, F)
     return dict(q=q, v=v, t=t, emax=emax, fext=np.zeros((N, 6)), step=int(step))
+
+
+def _upper21(M):
+    """Upper triangle, row-major, of a stack of symmetric 6 x 6 matrices."""
+    iu = np.triu_indices(6)
+    return np.ascontiguousarray(M[:, iu[0], iu[1]])
+
+
+def _rescale_dt(base, var):
+    base = {k: v for k, v in base.items() if k != "mass_block"}
+    r = lambda_max(base) / lambda_max(var)
+    var["dt"] = float(base["dt"]) * math.sqrt(min(r, 1.0))
+    var["meta"] = dict(var.get("meta", {}), dt_scale=math.sqrt(min(r, 1.0)),
+                       lambda_ratio=r)
+
+
+def mass_variant(sysd, kind):
+    """The specimen with another mass representation (eq. balance and the
+    section on the implementations' mass matrices):
+
+    - "lumped": the diagonal of each cell's rigid-body mass block (mass,
+      diagonal of the inertia tensor about the particle centre); the
+      generator's default;
+    - "cell_block": the full 6 x 6 rigid-body block of each cell about its
+      particle centre, [[m 1, -[c]x], [[c]x, J]] with c = m r (first moment,
+      r the centroid offset) and J the full inertia tensor, as `mass_block`
+      (N, 21: upper triangle, row-major, DoFs u_x, u_y, u_z, th_x, th_y,
+      th_z); its diagonal stays in mass / inertia;
+    - "sphere": point masses from an equal split of each tetrahedron's mass
+      (rho V_tet / 4 to each vertex) and an isotropic rotational inertia of
+      a solid sphere of the particle's diameter, m d^2 / 10.
+    The time step is scaled by sqrt(lambda_max(lumped) / lambda_max(variant))
+    of the assembled systems, when that is below 1, so that the stability
+    margin of the given step carries over.
+    Returns a new dict (arrays shared where unchanged)."""
+    out = dict(sysd)
+    out.pop("mass_block", None)
+    if kind == "lumped":
+        return out
+    if kind == "cell_block":
+        m = np.asarray(sysd["mass"], dtype=np.float64)
+        c = m[:, None] * np.asarray(sysd["cell_r"], dtype=np.float64)
+        J = np.asarray(sysd["cell_inertia"], dtype=np.float64)
+        N = m.size
+        M = np.zeros((N, 6, 6))
+        M[:, 0, 0] = M[:, 1, 1] = M[:, 2, 2] = m
+        cx = np.zeros((N, 3, 3))
+        cx[:, 0, 1], cx[:, 0, 2] = -c[:, 2], c[:, 1]
+        cx[:, 1, 0], cx[:, 1, 2] = c[:, 2], -c[:, 0]
+        cx[:, 2, 0], cx[:, 2, 1] = -c[:, 1], c[:, 0]
+        M[:, :3, 3:] = -cx
+        M[:, 3:, :3] = cx
+        M[:, 3:, 3:] = J
+        out["mass_block"] = _upper21(M)
+        out["inertia"] = np.ascontiguousarray(np.einsum("nii->ni", J))
+        _rescale_dt(sysd, out)
+        return out
+    if kind == "sphere":
+        x = np.asarray(sysd["x0"], dtype=np.float64)
+        tets = np.asarray(sysd["tet_nodes"], dtype=np.int64)
+        p = x[tets]
+        V = np.abs(np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])) / 6.0
+        rho = float(sysd["mass"].sum() / sysd["cell_vol"].sum())
+        m = np.zeros(x.shape[0])
+        np.add.at(m, tets.ravel(), np.repeat(rho * V / 4.0, 4))
+        d = np.asarray(sysd["diam"], dtype=np.float64)
+        out["mass"] = m
+        out["inertia"] = np.repeat((m * d ** 2 / 10.0)[:, None], 3, axis=1)
+        _rescale_dt(sysd, out)
+        return out
+    raise ValueError(f"unknown mass representation {kind!r}")
