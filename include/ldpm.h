@@ -148,6 +148,19 @@ typedef struct {
     void *(*dev_alloc)(size_t bytes, void *ctx);
     void (*dev_free)(void *ptr, void *ctx);
     void *alloc_ctx;
+    /* Mass representation (eq. balance: the cell's inertia tensors M_u,
+     * M_theta, I_u, I_theta).  NULL: the lumped diagonal (mass,
+     * rot_inertia), as the paper's explicit solvers use.  Otherwise the
+     * full rigid-body mass block of every cell about its particle centre,
+     * [21][N]: the upper triangle of the symmetric 6 x 6 block, row-major
+     * over (u_x, u_y, u_z, theta_x, theta_y, theta_z), i.e. entries
+     * (0,0) (0,1) .. (0,5) (1,1) .. (5,5); it must be positive definite
+     * (LDPM_ERR_ARG otherwise).  The step then solves, per particle, the
+     * free rows M_FF a_F = f_F - M_FP a_P with the prescribed DoFs'
+     * accelerations a_P, reports reactions (M a - f)_P and the kinetic
+     * energy 1/2 v^T M v.  mass and rot_inertia are still required
+     * (validation) but not used by the step.  Not with persistent launches. */
+    const double *mass_block;
 } ldpm_system_desc;
 
 /* Energies of one specimen after the last completed step n (all at time
@@ -208,8 +221,8 @@ ldpm_status ldpm_get_info(ldpm_system *s, ldpm_info *out);
  * facet kernel's tiles are remapped so that each XCD (own L2) works on a
  * contiguous range, and whether ldpm_step runs as one persistent
  * cooperative launch per chunk of steps (facet and particle phases separated
- * by grid barriers) instead of two kernels per step.  Results do not depend
- * on it (bitwise).                                                          */
+ * by grid barriers) instead of two kernels per step (lumped mass only).
+ * Results do not depend on it (bitwise).                                    */
 typedef struct {
     int32_t tets_per_block;
     int32_t particle_threads;

@@ -110,6 +110,7 @@ struct ldpm_system {
     unsigned* bar;
     int64_t* prog_off;
     double *prog_t, *prog_v, *progv, *red;
+    double* mblk = nullptr;  // full cell mass blocks [N][72] (M rows, then G rows), or none
     void *cI, *area, *frame, *ht, *hemax, *contrib;
     int64_t n_prog_pts = 0, n_prog = 0;
     MatDev<double> matd;
@@ -208,6 +209,58 @@ void to_r(std::vector<unsigned char>& buf, const double* src, size_t n)
 
 size_t rbytes(int prec) { return prec == LDPM_PREC_MIXED ? 4 : 8; }
 
+// Cholesky factor L (lower) of the sub-block of A on the index set idx (n
+// entries; idx == nullptr: the leading n x n block); false unless positive
+// definite
+bool cholesky_sub(const double A[6][6], const int* idx, int n, double L[6][6])
+{
+    for (int r = 0; r < n; r++)
+        for (int c = 0; c <= r; c++) {
+            const int ir = idx ? idx[r] : r, ic = idx ? idx[c] : c;
+            double acc = A[ir][ic];
+            for (int k = 0; k < c; k++) acc -= L[r][k] * L[c][k];
+            if (r == c) {
+                if (!(acc > 0.0)) return false;
+                L[r][r] = std::sqrt(acc);
+            } else {
+                L[r][c] = acc / L[c][c];
+            }
+        }
+    return true;
+}
+
+bool spd_ok(const double A[6][6], const int* idx, int n)
+{
+    double L[6][6];
+    return cholesky_sub(A, idx, n, L);
+}
+
+// G = inverse of A over the free index set fr (nf entries), embedded in
+// 6 x 6 with zero rows and columns elsewhere
+bool spd_inverse(const double A[6][6], const int* fr, int nf, double G[6][6])
+{
+    for (int r = 0; r < 6; r++)
+        for (int c = 0; c < 6; c++) G[r][c] = 0.0;
+    if (nf == 0) return true;
+    double L[6][6];
+    if (!cholesky_sub(A, fr, nf, L)) return false;
+    for (int j = 0; j < nf; j++) {  // column j of the inverse: L L^T x = e_j
+        double y[6], x[6];
+        for (int r = 0; r < nf; r++) {
+            double acc = (r == j) ? 1.0 : 0.0;
+            for (int k = 0; k < r; k++) acc -= L[r][k] * y[k];
+            y[r] = acc / L[r][r];
+        }
+        for (int r = nf - 1; r >= 0; r--) {
+            double acc = y[r];
+            for (int k = r + 1; k < nf; k++) acc -= L[k][r] * x[k];
+            x[r] = acc / L[r][r];
+        }
+        for (int r = 0; r < nf; r++) G[fr[r]][fr[j]] = x[r];
+    }
+    return true;
+}
+
 }  // namespace
 
 // Kernel launches.  With events (ev0, ev1) the launch is made with
@@ -289,25 +342,30 @@ static void launch_facet(ldpm_system* s, hipEvent_t ev0 = nullptr, hipEvent_t ev
     }
 }
 
-template <typename R>
+template <typename R, int FULLM>
 static void launch_particle_t(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
     ParticleArgs pa{s->node, s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
-                    s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N};
+                    s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N, s->mblk};
     const int th = s->launch.particle_threads;
     const unsigned nb = (unsigned)((s->N * PG + th - 1) / th);
     if (ev0)
-        hipExtLaunchKernelGGL(k_particle<R>, dim3(nb), dim3(th), 0, s->stream, ev0, ev1, 0, pa,
+        hipExtLaunchKernelGGL((k_particle<R, FULLM>), dim3(nb), dim3(th), 0, s->stream, ev0, ev1, 0, pa,
                               (const R*)s->contrib, s->step, s->dt);
     else
-        hipLaunchKernelGGL(k_particle<R>, dim3(nb), dim3(th), 0, s->stream, pa, (const R*)s->contrib, s->step,
-                           s->dt);
+        hipLaunchKernelGGL((k_particle<R, FULLM>), dim3(nb), dim3(th), 0, s->stream, pa, (const R*)s->contrib,
+                           s->step, s->dt);
 }
 
 static void launch_particle(ldpm_system* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    if (s->prec == LDPM_PREC_MIXED) launch_particle_t<float>(s, ev0, ev1);
-    else launch_particle_t<double>(s, ev0, ev1);
+    if (s->prec == LDPM_PREC_MIXED) {
+        if (s->mblk) launch_particle_t<float, 1>(s, ev0, ev1);
+        else launch_particle_t<float, 0>(s, ev0, ev1);
+    } else {
+        if (s->mblk) launch_particle_t<double, 1>(s, ev0, ev1);
+        else launch_particle_t<double, 0>(s, ev0, ev1);
+    }
 }
 
 // Persistent launch: chunks of at most PERSIST_CHUNK steps per cooperative
@@ -331,7 +389,7 @@ static hipError_t launch_persist_t(ldpm_system* s, int64_t nsteps)
                     s->F, s->E};
     ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
     ParticleArgs pa{s->node, s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
-                    s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N};
+                    s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N, s->mblk};
     GridSync gs{s->bar, s->bar + 1, s->flag};
     MatDev<R> mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
     const int32_t* pos = s->pos;
@@ -438,6 +496,32 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
         for (int c = 0; c < 3; c++)
             if (!(d->rot_inertia[c * N + i] > 0))
                 return fail(LDPM_ERR_ARG, "rot_inertia of particle %lld must be positive", (long long)i);
+    }
+    // full cell mass blocks: symmetric positive definite, and so is every
+    // free-DoF sub-block (Cholesky); G = inverse over the free DoFs
+    std::vector<double> mblk;
+    if (d->mass_block) {
+        if (!finite_all(d->mass_block, 21 * N)) return fail(LDPM_ERR_ARG, "non-finite mass_block");
+        mblk.assign((size_t)72 * N, 0.0);
+        for (int64_t i = 0; i < N; i++) {
+            double Mb[6][6];
+            for (int r = 0, k = 0; r < 6; r++)
+                for (int c = r; c < 6; c++, k++) Mb[r][c] = Mb[c][r] = d->mass_block[k * N + i];
+            int fr[6], nf = 0;
+            for (int dd = 0; dd < 6; dd++)
+                if (d->dof_mode[dd * N + i] == 0) fr[nf++] = dd;
+            if (!spd_ok(Mb, nullptr, 6))
+                return fail(LDPM_ERR_ARG, "mass_block of particle %lld is not positive definite", (long long)i);
+            double G[6][6];
+            if (!spd_inverse(Mb, fr, nf, G))
+                return fail(LDPM_ERR_ARG, "mass_block of particle %lld: free-DoF block not positive definite",
+                            (long long)i);
+            for (int r = 0; r < 6; r++)
+                for (int c = 0; c < 6; c++) {
+                    mblk[(size_t)72 * i + 6 * r + c] = Mb[r][c];
+                    mblk[(size_t)72 * i + 36 + 6 * r + c] = G[r][c];
+                }
+        }
     }
     // specimen of each particle (tets and facets must stay inside one specimen)
     std::vector<int32_t> spec_of(N);
@@ -555,6 +639,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     const size_t o_rec = cv.take<int32_t>(F), o_flag = cv.take<int32_t>(4), o_bar = cv.take<unsigned>(4);
     const size_t o_poff = cv.take<int64_t>(nP + 1), o_pt = cv.take<double>(npts + 1), o_pv = cv.take<double>(npts + 1);
     const size_t o_red = cv.take<double>(8);
+    const size_t o_mblk = mblk.empty() ? 0 : cv.take<double>(72 * N);
     const size_t o_progv = cv.take<double>(2 * nP + 2);
     cv.off = (cv.off + 255) & ~size_t(255);
     const size_t o_cI = cv.off; cv.off += 3 * F * rb;
@@ -603,6 +688,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->rec = (int32_t*)(B + o_rec); s->flag = (int32_t*)(B + o_flag); s->bar = (unsigned*)(B + o_bar);
     s->prog_off = (int64_t*)(B + o_poff); s->prog_t = (double*)(B + o_pt); s->prog_v = (double*)(B + o_pv);
     s->red = (double*)(B + o_red);
+    s->mblk = mblk.empty() ? nullptr : (double*)(B + o_mblk);
     s->progv = (double*)(B + o_progv);
     s->cI = B + o_cI; s->area = B + o_area; s->frame = B + o_frame;
     s->ht = B + o_ht; s->hemax = B + o_hem; s->contrib = B + o_con;
@@ -638,6 +724,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     }
     CK(H2D(s->node, nodes.data(), 16 * N * 8));
     CK(H2D(s->mass, d->mass, N * 8));
+    if (s->mblk) CK(H2D(s->mblk, mblk.data(), 72 * N * 8));
     CK(H2D(s->inertia, d->rot_inertia, 3 * N * 8));
     CK(H2D(s->scale, d->dof_scale, 6 * N * 8));
     if (s->body) CK(H2D(s->body, body.data(), 6 * N * 8));
@@ -688,9 +775,15 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
             double w = 0.0;
             for (int64_t i = poff[sp]; i < poff[sp + 1]; i++)
                 for (int dd = 0; dd < 6; dd++) {
-                    const double M = dd < 3 ? d->mass[i] : d->rot_inertia[(dd - 3) * N + i];
                     const double vv = v0[dd * N + i];
-                    w += 0.5 * M * vv * vv;
+                    if (!mblk.empty()) {
+                        double mv = 0.0;
+                        for (int k = 0; k < 6; k++) mv += mblk[(size_t)72 * i + 6 * dd + k] * v0[k * N + i];
+                        w += 0.5 * vv * mv;
+                    } else {
+                        const double M = dd < 3 ? d->mass[i] : d->rot_inertia[(dd - 3) * N + i];
+                        w += 0.5 * M * vv * vv;
+                    }
                 }
             s->wkin0[sp] = w;
         }
@@ -856,6 +949,7 @@ ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
     //   q, v, fext read + written (3 x 6 x 16 B), mass + inertia 32 B, scale 48 B,
     //   prog 24 B, mode 6 B, w_ext r+w 16 B, w_kin 8 B
     o->particle_kernel_bytes = T * 24.0 * rb + N * (4.0 + 288.0 + 32.0 + 48.0 + 24.0 + 6.0 + 16.0 + 8.0);
+    if (s->mblk) o->particle_kernel_bytes += N * 576.0;  // mass block M and G
     o->device_bytes = s->arena_bytes;
     return LDPM_OK;
 }
@@ -867,6 +961,8 @@ ldpm_status ldpm_set_launch(ldpm_system* s, const ldpm_launch* c)
         return fail(LDPM_ERR_ARG, "tets_per_block must be 8, 16, 32 or 64");
     if (c->particle_threads < 64 || c->particle_threads > 1024 || c->particle_threads % 64)
         return fail(LDPM_ERR_ARG, "particle_threads must be a multiple of 64 in [64, 1024]");
+    if (c->persistent && s->mblk)
+        return fail(LDPM_ERR_ARG, "the persistent launch supports the lumped diagonal mass only");
     s->launch = *c;
     s->launch.xcd_remap = c->xcd_remap ? 1 : 0;
     s->launch.persistent = c->persistent ? 1 : 0;
@@ -884,11 +980,11 @@ namespace {
 struct TuneKey {
     std::string arch;
     int64_t N, T, F, E, nspec;
-    int32_t prec, law;
+    int32_t prec, law, fullm;
     bool operator==(const TuneKey& o) const
     {
         return arch == o.arch && N == o.N && T == o.T && F == o.F && E == o.E && nspec == o.nspec &&
-               prec == o.prec && law == o.law;
+               prec == o.prec && law == o.law && fullm == o.fullm;
     }
 };
 struct TuneEntry {
@@ -920,7 +1016,7 @@ ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* 
     if (steps_per_trial <= 0) return fail(LDPM_ERR_ARG, "steps_per_trial must be positive");
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, s->device));
-    TuneKey key{prop.gcnArchName, s->N, s->T, s->F, s->E, s->nspec, s->prec, s->law};
+    TuneKey key{prop.gcnArchName, s->N, s->T, s->F, s->E, s->nspec, s->prec, s->law, s->mblk ? 1 : 0};
     for (const auto& t : g_tune_cache)
         if (t.key == key) {
             s->launch = t.best;
@@ -960,7 +1056,8 @@ ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* 
     for (int i = 0; i < 4; i++)
         for (int j = 0; j < 4; j++)
             for (int rm = 0; rm < 2; rm++) cands.push_back(ldpm_launch{tbs[i], pts[j], rm, 0});
-    for (int i = 0; i < 4; i++) cands.push_back(ldpm_launch{tbs[i], 256, 0, 1});
+    if (!s->mblk)
+        for (int i = 0; i < 4; i++) cands.push_back(ldpm_launch{tbs[i], 256, 0, 1});
     double best_t = 1e300;
     ldpm_launch best_l = keep;
     int32_t nt = 0;

@@ -95,6 +95,10 @@ struct ParticleArgs {
     const double* __restrict__ progv;    // [2P] program values of this step
     int32_t* __restrict__ flag;
     int64_t N;
+    // full cell mass blocks, [N][72]: M (6 x 6 rows) then G (6 x 6 rows),
+    // G = inverse of M over the free DoFs, zero rows/columns for prescribed
+    // ones; nullptr with the lumped diagonal
+    const double* __restrict__ mblk;
 };
 
 // ---------------------------------------------------------------------------
@@ -560,7 +564,11 @@ constexpr int PG = 16;
 
 // Particle I = gt / PG, lane gt % PG (gt: a global lane index; groups of PG
 // lanes are aligned within a wave and take the branch together).
-template <typename R>
+// FULLM: the particle's 6 x 6 cell mass block couples its DoFs (eq.
+// balance): prescribed DoFs take their programmed velocity, whose
+// acceleration a_P enters the free rows, a_F = G (f_net - M a_P); the
+// reactions are (M a)_P - f_net,P and the kinetic energy 1/2 vb^T M vb.
+template <typename R, int FULLM>
 __device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& pa, const R* __restrict__ contrib,
                                                int64_t n, double dt)
 {
@@ -571,7 +579,7 @@ __device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& p
     // per-DoF data of lane d < 6, loaded before the gather
     const int d = lane < 6 ? lane : 0;
     const int64_t id = d * N + I;
-    const double M = d < 3 ? pa.mass[I] : pa.inertia[(d - 3) * N + I];
+    const double M = FULLM ? 0.0 : (d < 3 ? pa.mass[I] : pa.inertia[(d - 3) * N + I]);
     const double bodyf = pa.body ? pa.body[id] : 0.0;
     const int32_t pg = pa.prog[id];
     const uint8_t md = pa.mode[id];
@@ -579,6 +587,15 @@ __device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& p
     const double vold = pa.node[I * 16 + 6 + d];
     const double fold = pa.fext[id];
     const double qold = pa.node[I * 16 + d];
+    double mrow[6], grow[6];
+    if constexpr (FULLM) {
+        const double* mb = pa.mblk + I * 72 + d * 6;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            mrow[k] = mb[k];
+            grow[k] = mb[36 + k];
+        }
+    }
     double f[6] = {0, 0, 0, 0, 0, 0};
     const int32_t s0 = pa.ptr[I], s1 = pa.ptr[I + 1];
     for (int32_t s = s0 + lane; s < s1; s += PG) {
@@ -593,11 +610,50 @@ __device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& p
     }
     double wk = 0.0, dwe = 0.0;
     bool bad = false;
-    if (lane < 6) {
+    const double h = (n == 0) ? 0.5 * dt : dt;
+    if constexpr (FULLM) {
         double fd = f[0];
 #pragma unroll
         for (int k = 1; k < 6; k++) fd = (d == k) ? f[k] : fd;
-        const double h = (n == 0) ? 0.5 * dt : dt;
+        double applied = bodyf;
+        if (md == 0 && pg >= 0) applied += scl * pa.progv[2 * pg];
+        const double fnet = fd + applied;
+        double vnew = 0.0, acc = 0.0;
+        if (md != 0) {
+            vnew = (pg >= 0) ? scl * pa.progv[2 * pg + 1] : 0.0;
+            acc = (vnew - vold) / h;
+        }
+        // z = f_net - M a_P (row d), then a_F = G z
+        double z = fnet;
+#pragma unroll
+        for (int k = 0; k < 6; k++) z -= mrow[k] * __shfl(acc, k, PG);
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) a += grow[k] * __shfl(z, k, PG);
+        if (md == 0) {
+            acc = a;
+            vnew = vold + h * a;
+        }
+        double ma = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) ma += mrow[k] * __shfl(acc, k, PG);
+        const double Fd = (md == 0) ? applied : applied + (ma - fnet);  // reaction on prescribed DoFs
+        const double vb = (n == 0) ? vold : 0.5 * (vold + vnew);
+        double mvb = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) mvb += mrow[k] * __shfl(vb, k, PG);
+        if (lane < 6) {
+            if (n > 0) dwe = 0.5 * (fold + Fd) * (dt * vold);
+            wk = 0.5 * vb * mvb;
+            pa.fext[id] = Fd;
+            pa.node[I * 16 + 6 + d] = vnew;
+            pa.node[I * 16 + d] = qold + dt * vnew;
+            bad = !isfinite(vnew);
+        }
+    } else if (lane < 6) {
+        double fd = f[0];
+#pragma unroll
+        for (int k = 1; k < 6; k++) fd = (d == k) ? f[k] : fd;
         double applied = bodyf;
         if (md == 0 && pg >= 0) applied += scl * pa.progv[2 * pg];
         const double fnet = fd + applied;
@@ -632,11 +688,11 @@ __device__ __forceinline__ void particle_group(int64_t gt, const ParticleArgs& p
     if (bad) pa.flag[0] = 1;
 }
 
-template <typename R>
+template <typename R, int FULLM>
 __global__ __launch_bounds__(1024) void k_particle(ParticleArgs pa, const R* __restrict__ contrib,
                                                    int64_t n, double dt)
 {
-    particle_group<R>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, pa, contrib, n, dt);
+    particle_group<R, FULLM>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, pa, contrib, n, dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -704,7 +760,7 @@ __global__ __launch_bounds__(12 * TB) void k_persist(NodeArgs na, FacetArgs<R> f
             facet_tile<R, LAW, TB, MODE_PLAIN>(blk, blk == 0, na, fa, mat, pos, contrib, wint, pr, n, dt, sg, cp);
         if (!grid_barrier(gs, G)) return;
         for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < lanes; gt += (int64_t)G * blockDim.x)
-            particle_group<R>(gt, pa, contrib, n, dt);
+            particle_group<R, 0>(gt, pa, contrib, n, dt);
         if (!grid_barrier(gs, G)) return;
     }
 }

@@ -66,7 +66,7 @@ class SystemDesc(C.Structure):
                 ("body_force", _dp), ("q0", _dp), ("v0", _dp), ("init_state", C.POINTER(State)),
                 ("mat", C.POINTER(Material)), ("dt", C.c_double), ("precision", C.c_int32),
                 ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("mass_block", _dp)]
 
 
 class Energies(C.Structure):
@@ -284,6 +284,11 @@ def make_desc(sysd, precision="fp64"):
     d.mat = C.pointer(mat)
     d.dt = float(sysd["dt"])
     d.precision = PREC[precision]
+    if sysd.get("mass_block") is not None:
+        k["mblk"] = _soa(sysd["mass_block"])
+        if k["mblk"].shape != (21, N):
+            raise ValueError("mass_block must have shape (N, 21)")
+        d.mass_block = _p(k["mblk"], _dp)
     return d, k
 
 

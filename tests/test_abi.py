@@ -60,6 +60,10 @@ def _set(key, idx, val):
     ("nan_geom", _set("facet_cI", (7, 1), float("nan")), "non-finite"),
     ("dof_mode", _set("dof_mode", (0, 0), 7), "dof_mode"),
     ("dof_prog", _set("dof_prog", (0, 0), 5), "dof_prog"),
+    ("mass_block_not_pd", lambda s: s.__setitem__("mass_block", np.zeros((s["x0"].shape[0], 21))),
+     "positive definite"),
+    ("mass_block_nan", lambda s: s.__setitem__("mass_block", np.full((s["x0"].shape[0], 21), np.nan)),
+     "non-finite mass_block"),
 ])
 def test_invalid_systems_are_rejected(name, mod, msg):
     rc, err, h = _load(mod)
