@@ -294,6 +294,79 @@ def crack_case(sysd, g64, gmx, h64, total):
     return rec
 
 
+def spectrum_peaks(x, dt, k=4):
+    """The k lowest clear peaks (> 5 % of the largest) of the amplitude
+    spectrum of x (mean removed, Hann window), parabolic interpolation."""
+    x = np.asarray(x, float) - np.mean(x)
+    a = np.abs(np.fft.rfft(x * np.hanning(x.size)))
+    f = np.fft.rfftfreq(x.size, dt)
+    thr = 0.05 * a[1:].max()
+    out = []
+    for i in range(2, a.size - 1):
+        if a[i] > thr and a[i] >= a[i - 1] and a[i] > a[i + 1]:
+            y0, y1, y2 = np.log(a[i - 1]), np.log(a[i]), np.log(a[i + 1])
+            off = 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+            out.append(float((i + off) * (f[1] - f[0])))
+            if len(out) == k:
+                break
+    return out
+
+
+def mass_case(args):
+    """Mass representations (eq. balance; the implementations' mass
+    matrices): free vibration of the 50 mm elastic cube with the lumped
+    diagonal, the full rigid-cell blocks and the sphere inertia, same dt;
+    spectrum peaks of a top corner node's u_x.  Plus the particle kernel's
+    time with the blocks on the tension cube."""
+    import torch
+    from paper_2603_13190_amd import specimen as S
+    from paper_2603_13190_amd.ldpm import System
+    base = S.elastic_vibration_cube(edge=50.0, d0=4.0, da=8.0, seed=1)
+    variants = {"lumped": base, "cell_block": S.mass_variant(base, "cell_block"),
+                "sphere": S.mass_variant(base, "sphere")}
+    dt = min(v["dt"] for v in variants.values())
+    x = base["x0"]
+    corner = int(np.argmax(x[:, 0] + x[:, 1] + x[:, 2]))
+    every, n = 20, args.mass_steps
+    rec = {"workload": "free vibration, 50 mm elastic cube, d 4-8 mm, seed 1, base fixed, "
+                       "initial v_x = 10 sin(pi z / 2H) mm/s", "dt": dt, "steps": n,
+           "signal": f"u_x of the top corner node {corner}, every {every} steps"}
+    for name, sysd in variants.items():
+        g = System(dict(sysd, dt=dt))
+        sig = []
+        for _ in range(n // every):
+            g.step(every)
+            sig.append(g.read_state()["q"][corner, 0])
+        en = g.energy()
+        rec[name] = {"peaks_Hz": spectrum_peaks(sig, every * dt), "energy_err": en["err"],
+                     "dt_stable_scale": sysd.get("meta", {}).get("dt_scale", 1.0)}
+        g.close()
+        log(f"free vibration {name}: peaks {['%.0f' % f for f in rec[name]['peaks_Hz']]} Hz, "
+            f"energy err {en['err']:.2e}")
+    ref = rec["lumped"]["peaks_Hz"]
+    for name in ("cell_block", "sphere"):
+        pk = rec[name]["peaks_Hz"]
+        rec[name]["rel_diff_vs_lumped"] = [float(b / a - 1) for a, b in zip(ref, pk)]
+    # particle kernel with the blocks on the tension cube (same steps)
+    ten = S.tension_cube(edge=100.0, d0=4.0, da=10.0, seed=1, rate=1e-2, ramp=1e-3)
+    tb = S.mass_variant(ten, "cell_block")
+    for name, sysd in (("lumped", ten), ("cell_block", dict(tb, dt=ten["dt"]))):
+        g = System(sysd)
+        g.step(1000)
+        torch.cuda.synchronize()
+        fms, pms = g.step_profiled(2000)
+        info = g.info()
+        rec[f"tension_cube100_{name}"] = {
+            "facet_kernel_avg_us": fms / 2000 * 1e3, "particle_kernel_avg_us": pms / 2000 * 1e3,
+            "particle_kernel_bytes": info["particle_kernel_bytes"],
+            "particle_kernel_GBs": info["particle_kernel_bytes"] / (pms / 2000 * 1e-3) / 1e9}
+        g.close()
+    log(f"particle kernel on the tension cube: lumped "
+        f"{rec['tension_cube100_lumped']['particle_kernel_avg_us']:.2f} us, cell blocks "
+        f"{rec['tension_cube100_cell_block']['particle_kernel_avg_us']:.2f} us")
+    return rec
+
+
 def cycle_run(sysd, precision, model=None, every=1000, launch=None):
     """Whole cyclic trajectory; nominal stress history, energy error, timing
     (reaction sampling outside the timed spans), surrogate share."""
@@ -479,6 +552,8 @@ def main():
     ap.add_argument("--cyl-full-d0", type=float, default=1.1)
     ap.add_argument("--large-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-mass", action="store_true", help="skip the mass-representation case")
+    ap.add_argument("--mass-steps", type=int, default=60000)
     ap.add_argument("--no-crack", action="store_true",
                     help="skip the crack-pattern comparison and the perturbation study")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -606,6 +681,12 @@ def main():
         gaccmx.close()
     elif not args.no_accuracy and "load_prog" in sysd["meta"]:
         gacc64.close()
+
+    # ---- mass representations: free-vibration spectra, particle kernel ----
+    if not args.no_mass:
+        r = optional("mass", lambda: mass_case(args))
+        if r is not None:
+            out["mass"] = r
 
     # ---- batched: 64 uneven specimens in one system (window of steps) ----
     if not args.no_batch:
