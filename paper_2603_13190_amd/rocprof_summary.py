@@ -20,7 +20,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ldpm.hip", "step_kernels.hpp", "law.hpp")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ldpm.hip", "step_kernels.hpp", "law.hpp", "mlp.hpp")]
 
 
 def source_sha1():
