@@ -74,6 +74,8 @@ def lib():
         L.ora_max_threads.restype = C.c_int
         L.ora_perturb.argtypes = [C.POINTER(OraSys), C.POINTER(OraState), _dp]
         L.ora_perturb.restype = C.c_double
+        L.ora_trial_force.argtypes = [C.POINTER(OraSys), C.POINTER(OraState)] + [_dp] * 6
+        L.ora_trial_force.restype = None
         _lib = L
     return _lib
 

@@ -592,6 +592,55 @@ double ora_perturb(const ora_sys *s, ora_state *st, const double *delta)
     return W;
 }
 
+/* Trial internal force of an implicit iteration: every facet law is
+ * evaluated at the trial configuration q from the committed history (strain
+ * e, traction t, e_max of the state) without committing it.  g = -f_int(q)
+ * (the contribution to M q'' as in the explicit step, ascending facet
+ * order); t_out, e_out, emax_out: the trial history; dW: the trial
+ * internal-work increment of each facet (trapezoid).                      */
+void ora_trial_force(const ora_sys *s, const ora_state *st, const double *q, double *g, double *t_out,
+                     double *e_out, double *emax_out, double *dW)
+{
+    const int64_t N = s->N, T = s->T, F = s->F;
+    double *eV = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+    double *Fk = (double *)malloc(sizeof(double) * 3 * (size_t)(F > 0 ? F : 1));
+    tet_volstrains(s, q, eV);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < F; k++) {
+        double e[3], t[3], em;
+        ora_facet_strain(q + 6 * (int64_t)s->fI[k], q + 6 * (int64_t)s->fJ[k], s->cI + 3 * k, s->n + 3 * k,
+                         s->m + 3 * k, s->len[k], e);
+        ora_facet_law(&s->mat, s->len[k], e, st->e + 3 * k, eV[s->ftet[k]], st->t + 3 * k, st->emax[k], t, &em);
+        double w = 0.0;
+        for (int i = 0; i < 3; i++) w += 0.5 * (st->t[3 * k + i] + t[i]) * (e[i] - st->e[3 * k + i]);
+        dW[k] = s->A[k] * s->len[k] * w;
+        facet_force(s, k, t, Fk + 3 * k);
+        for (int i = 0; i < 3; i++) {
+            e_out[3 * k + i] = e[i];
+            t_out[3 * k + i] = t[i];
+        }
+        emax_out[k] = em;
+    }
+    memset(g, 0, sizeof(double) * 6 * (size_t)N);
+    for (int64_t k = 0; k < F; k++) {
+        const double *Fv = Fk + 3 * k;
+        const double *cI = s->cI + 3 * k;
+        double cJ[3], MI[3], MJ[3];
+        for (int i = 0; i < 3; i++) cJ[i] = cI[i] - s->len[k] * s->n[3 * k + i];
+        cross3(cI, Fv, MI);
+        cross3(cJ, Fv, MJ);
+        double *gI = g + 6 * (int64_t)s->fI[k], *gJ = g + 6 * (int64_t)s->fJ[k];
+        for (int i = 0; i < 3; i++) {
+            gI[i] += Fv[i];
+            gI[3 + i] += MI[i];
+            gJ[i] -= Fv[i];
+            gJ[3 + i] -= MJ[i];
+        }
+    }
+    free(eV);
+    free(Fk);
+}
+
 /* All facet strains for a given q (test helper). */
 void ora_all_strains(const ora_sys *s, const double *q, double *e)
 {
