@@ -10,7 +10,8 @@ kernels and of the calibration copy kernel (a plain device-to-device copy of
 a known number of bytes), scales the facet-kernel counters by
 known_bytes / counter_of_copy, and records them with the SHA-1 of the kernel
 sources, so that a later benchmark reports the traffic only while the kernel
-is unchanged.
+is unchanged (the SHA-1 covers the step kernels' device sources and the
+build flags).
 """
 import csv
 import hashlib
@@ -20,7 +21,10 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ldpm.hip", "step_kernels.hpp", "law.hpp", "mlp.hpp")]
+# the sources that define the step kernels' machine code (device code and
+# compile flags); host-side changes elsewhere do not invalidate the counters
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("step_kernels.hpp", "law.hpp", "mlp.hpp")] + \
+    [os.path.join(HERE, "build.py")]
 
 
 def source_sha1():
