@@ -10,6 +10,7 @@ errors against the FP64 path, the facet kernel's HBM roofline fraction
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -367,6 +368,85 @@ def mass_case(args):
     return rec
 
 
+def implicit_case(args):
+    """Implicit HHT-alpha against the explicit step (the paper's central
+    comparison): the tension cube's first 10k explicit steps (the loading
+    ramp and the elastic rise) with the implicit step 10 and 50 times larger,
+    the paper's convergence tolerance 1e-4 and 100-iteration cap; and free
+    vibration of the 50 mm elastic cube with the trapezoidal rule at 20
+    explicit steps per step (spectrum peaks against the explicit run)."""
+    import torch
+    from paper_2603_13190_amd import specimen as S
+    from paper_2603_13190_amd.ldpm import System
+    ten = S.tension_cube(edge=100.0, d0=4.0, da=10.0, seed=1, rate=1e-2, ramp=1e-3)
+    F = ten["meta"]["F"]
+    prog, area = ten["meta"]["load_prog"], ten["meta"]["area"]
+    n_exp = 10000
+    rec = {"workload": "tension_cube100, first 10k explicit steps (loading ramp and elastic rise)",
+           "explicit_dt": ten["dt"], "newton_tol": 1e-4, "max_iter": 100, "alpha": -0.1, "cg_tol": 1e-8}
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    g = System(ten)
+    a.record()
+    g.step(n_exp)
+    b.record()
+    torch.cuda.synchronize()
+    ms_e = a.elapsed_time(b)
+    s_e = g.reaction(prog) / area
+    rec["explicit"] = {"steps": n_exp, "ms": ms_e, "stress_MPa": s_e, "energy_err": g.energy()["err"]}
+    g.close()
+    for r in (10, 50):
+        g = System(ten)
+        t0 = time.perf_counter()
+        st = g.implicit_step(n_exp // r, r * ten["dt"], alpha=-0.1, tol=1e-4, max_iter=100, cg_tol=1e-8,
+                             cg_max_iter=20000)
+        wall = time.perf_counter() - t0
+        s_i = g.reaction(prog) / area
+        en = g.energy()
+        rec[f"implicit_{r}x"] = {
+            "steps": n_exp // r, "dt": r * ten["dt"], "ms": wall * 1e3, "time_vs_explicit": wall * 1e3 / ms_e,
+            "newton_per_step": st["newton_iters"] / st["steps"],
+            "cg_per_solve": st["cg_iters"] / max(st["newton_iters"], 1), "not_converged": st["not_converged"],
+            "stress_MPa": s_i, "stress_rel_diff_vs_explicit": abs(s_i - s_e) / abs(s_e), "energy_err": en["err"]}
+        g.close()
+        log(f"implicit {r}x: {wall * 1e3:.0f} ms vs explicit {ms_e:.0f} ms for the same span, "
+            f"{st['newton_iters'] / st['steps']:.1f} Newton/step, {st['cg_iters'] / max(st['newton_iters'], 1):.0f} "
+            f"CG/solve, stress {s_i:.4f} vs {s_e:.4f} MPa")
+    # free vibration: trapezoidal rule at 20 explicit steps per step
+    base = S.elastic_vibration_cube(edge=50.0, d0=4.0, da=8.0, seed=1)
+    x = base["x0"]
+    corner = int(np.argmax(x[:, 0] + x[:, 1] + x[:, 2]))
+    dte = base["dt"]
+    n = args.mass_steps
+    sig_e, sig_i = [], []
+    ge = System(base)
+    for _ in range(n // 20):
+        ge.step(20)
+        sig_e.append(ge.read_state()["q"][corner, 0])
+    ge.close()
+    gi = System(base)
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(n // 20):
+        st = gi.implicit_step(1, 20 * dte, alpha=0.0, tol=1e-10, max_iter=5, cg_tol=1e-12, cg_max_iter=20000)
+        iters += st["cg_iters"]
+        sig_i.append(gi.read_state()["q"][corner, 0])
+    wall = time.perf_counter() - t0
+    pe, pi = spectrum_peaks(sig_e, 20 * dte), spectrum_peaks(sig_i, 20 * dte)
+    w = [2 * math.pi * f for f in pe]
+    elong = [math.atan(wi * 20 * dte / 2) * 2 / (20 * dte) / wi - 1 for wi in w]
+    rec["free_vibration"] = {
+        "workload": "50 mm elastic cube, base fixed, initial v_x = 10 sin(pi z / 2H) mm/s", "explicit_dt": dte,
+        "implicit_dt": 20 * dte, "steps_explicit": n, "peaks_explicit_Hz": pe, "peaks_implicit_Hz": pi,
+        "rel_diff": [float(b / a_ - 1) for a_, b in zip(pe, pi)],
+        "trapezoidal_period_elongation_expected": elong, "energy_err_implicit": gi.energy()["err"],
+        "cg_per_step": iters / (n // 20), "wall_s": wall}
+    gi.close()
+    log(f"free vibration trapezoidal 20x: peaks {['%.0f' % f for f in pi]} Hz vs explicit "
+        f"{['%.0f' % f for f in pe]} Hz")
+    return rec
+
+
 def cycle_run(sysd, precision, model=None, every=1000, launch=None):
     """Whole cyclic trajectory; nominal stress history, energy error, timing
     (reaction sampling outside the timed spans), surrogate share."""
@@ -553,6 +633,7 @@ def main():
     ap.add_argument("--large-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mass", action="store_true", help="skip the mass-representation case")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-integration case")
     ap.add_argument("--mass-steps", type=int, default=60000)
     ap.add_argument("--no-crack", action="store_true",
                     help="skip the crack-pattern comparison and the perturbation study")
@@ -687,6 +768,12 @@ def main():
         r = optional("mass", lambda: mass_case(args))
         if r is not None:
             out["mass"] = r
+
+    # ---- implicit HHT-alpha against the explicit step ----
+    if not args.no_implicit:
+        r = optional("implicit", lambda: implicit_case(args))
+        if r is not None:
+            out["implicit"] = r
 
     # ---- batched: 64 uneven specimens in one system (window of steps) ----
     if not args.no_batch:

@@ -181,7 +181,8 @@ typedef struct {
  * device memory and upload.  On success *out owns everything.             */
 ldpm_status ldpm_load_system(const ldpm_system_desc *desc, ldpm_system **out);
 
-/* Enqueue n_steps explicit steps on the handle's stream (asynchronous). */
+/* Enqueue n_steps explicit steps on the handle's stream (asynchronous);
+ * LDPM_ERR_STATE on a handle that integrates implicitly. */
 ldpm_status ldpm_step(ldpm_system *s, int64_t n_steps);
 
 /* Like ldpm_step, but brackets every facet-kernel and particle-kernel launch
@@ -347,7 +348,8 @@ ldpm_status ldpm_capture_end(ldpm_system *s, float *rows, int64_t max_rows, int6
  * E = E0 diag(1, alpha, alpha), e and t the strain and traction of the last
  * law evaluation (configuration q^{n-1} = q^n - dt v^{n-1/2}; before the
  * first step the undeformed one), and only a positive normal inelastic
- * strain opening a crack: w_N = max(w_N, 0).                               */
+ * strain opening a crack: w_N = max(w_N, 0).  After implicit steps the last
+ * law evaluation is at the committed q_n itself.                           */
 ldpm_status ldpm_crack_opening(ldpm_system *s, double *w);
 
 /* Volumetric strain e_V of every tetrahedron at the configuration of the
@@ -393,8 +395,50 @@ ldpm_status ldpm_compare_fields(const double *x, const double *ref, int64_t n, d
  * surrogate installed the jump still goes through the exact law, and a
  * capture records nothing for it.  *work (may be NULL) receives the work of
  * this jump over all specimens.  Synchronises the stream.  The first call
- * allocates a device buffer of about 8 (6N + 2T) bytes, kept by the handle. */
+ * allocates a device buffer of about 8 (6N + 2T) bytes, kept by the handle.
+ * Explicit runs only (LDPM_ERR_STATE after implicit steps).               */
 ldpm_status ldpm_perturb(ldpm_system *s, const double *delta, double *work);
+
+/* ---- Implicit HHT-alpha integration --------------------------------------
+ * The paper's implicit solvers integrate the same equations with the HHT
+ * (Hilber-Hughes-Taylor) alpha or generalised-alpha methods and Newton-type
+ * iterations.  ldpm_implicit_step advances n_steps steps of the HHT-alpha
+ * method (beta = (1 - alpha)^2 / 4, gamma = 1/2 - alpha):
+ *   M a_{n+1} = (1 + alpha)(g(q_{n+1}) + f_{n+1}) - alpha (g(q_n) + f_n) + R_{n+1},
+ *   q_{n+1} = q_n + dt v_n + dt^2 ((1/2 - beta) a_n + beta a_{n+1}),
+ *   v_{n+1} = v_n + dt ((1 - gamma) a_n + gamma a_{n+1}),
+ * g = -f_int (the gathered facet forces), f the applied forces, R the
+ * reactions of prescribed DoFs, which move by dt v_P(t_n + dt/2).  Each step
+ * is solved by modified Newton on the free DoFs with the initial elastic
+ * stiffness K0: K_eff = M / (beta dt^2) + (1 + alpha) K0, its systems solved
+ * by Jacobi-preconditioned conjugate gradients with K0 applied matrix-free
+ * (the facet kernel of the elastic law).  Every Newton iteration evaluates
+ * the facet law at the trial configuration from the committed history; the
+ * last trial is committed when the step is accepted: when
+ * |R_F|_2 <= tol (|(M a)_F|_2 + |rhs_F|_2) or after max_iter iterations
+ * (counted in not_converged).  The predictor keeps the acceleration.
+ * The state then holds q_n, v_n (not the explicit scheme's mid-step
+ * velocities): a handle integrates either explicitly or implicitly
+ * (LDPM_ERR_STATE otherwise), and dt and alpha stay fixed after the first
+ * implicit step.  FP64, lumped mass, no surrogate or capture.  Energies as
+ * for the explicit step (W_int facet trapezoids of accepted steps, W_ext the
+ * trapezoid of applied + reaction forces, W_kin = 1/2 v^T M v) at
+ * t_n = n dt.  The first call allocates device buffers of about
+ * 8 (120 N + 7 F + 26 T) bytes, kept by the handle.  Synchronises.          */
+typedef struct {
+    double dt;           /* implicit time step (> 0) */
+    double alpha;        /* HHT alpha in [-1/3, 0] (0: trapezoidal rule) */
+    double tol;          /* relative Newton tolerance (> 0) */
+    int32_t max_iter;    /* Newton iterations per step (>= 1) */
+    double cg_tol;       /* relative residual of the CG solves (> 0) */
+    int32_t cg_max_iter; /* CG iterations per solve (>= 1) */
+} ldpm_implicit_opts;
+typedef struct {
+    int64_t steps, newton_iters, cg_iters, not_converged;
+    double max_residual; /* largest relative Newton residual of an accepted step */
+} ldpm_implicit_stats;
+ldpm_status ldpm_implicit_step(ldpm_system *s, const ldpm_implicit_opts *opts, int64_t n_steps,
+                               ldpm_implicit_stats *stats);
 
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);

@@ -1,0 +1,432 @@
+// Device side of the implicit HHT-alpha integrator: per-DoF vector kernels,
+// the deterministic gather of tet-node records into particle vectors, the
+// diagonal of the initial elastic stiffness, and the conjugate-gradient
+// kernels of the modified-Newton solves.  Vectors are [6][N] doubles.
+// Included once, by ldpm.hip, after step_kernels.hpp.
+#pragma once
+
+constexpr int IM_THREADS = 256;
+constexpr int IM_MAX_BLOCKS = 1024;
+
+// fixed-order block sum of three values (IM_THREADS lanes)
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c)
+{
+    __shared__ double s[3][IM_THREADS];
+    s[0][threadIdx.x] = a;
+    s[1][threadIdx.x] = b;
+    s[2][threadIdx.x] = c;
+    __syncthreads();
+    for (int w = IM_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + w];
+            s[1][threadIdx.x] += s[1][threadIdx.x + w];
+            s[2][threadIdx.x] += s[2][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    a = s[0][0];
+    b = s[1][0];
+    c = s[2][0];
+    __syncthreads();
+}
+
+// partials [3][G] -> out[0..2] (one block, fixed order)
+__global__ __launch_bounds__(IM_THREADS) void k_im_reduce3(const double* __restrict__ part, int G,
+                                                           double* __restrict__ out)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < G; i += IM_THREADS) {
+        a += part[i];
+        b += part[G + i];
+        c += part[2 * G + i];
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+        out[2] = c;
+    }
+}
+
+// out[k][I] = sum of the tet-node records of particle I (CSR order, PG lanes
+// per particle, the same summation structure as the step's gather)
+template <typename R>
+__global__ __launch_bounds__(256) void k_im_gather(const int32_t* __restrict__ ptr, const R* __restrict__ contrib,
+                                                   int64_t N, double* __restrict__ out)
+{
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t I = gt / PG;
+    const int lane = (int)(gt % PG);
+    if (I >= N) return;
+    double f[6] = {0, 0, 0, 0, 0, 0};
+    const int32_t s0 = ptr[I], s1 = ptr[I + 1];
+    for (int32_t s = s0 + lane; s < s1; s += PG) {
+        const R* c = contrib + (int64_t)s * 6;
+#pragma unroll
+        for (int k = 0; k < 6; k++) f[k] += (double)c[k];
+    }
+#pragma unroll
+    for (int off = PG / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) f[k] += __shfl_xor(f[k], off, PG);
+    }
+    if (lane < 6) {
+        double v = f[0];
+#pragma unroll
+        for (int k = 1; k < 6; k++) v = (lane == k) ? f[k] : v;
+        out[(int64_t)lane * N + I] = v;
+    }
+}
+
+// Diagonal of the initial elastic stiffness, per tet node (t, a) in
+// incidence order: for every facet of tet t at node a, with B_a = [-1, [c^I]x]
+// (a = I) or [1, -[c^J]x] (a = J) and D = E0 (alpha 1 + (1 - alpha) n n^T),
+// (A / l) b_d^T D b_d for each column b_d of B_a.
+template <typename R>
+__global__ __launch_bounds__(256) void k_im_diag_k0(const FacetArgs<R> fa, const int32_t* __restrict__ pos, int64_t T,
+                                                    double E0, double alpha, double* __restrict__ out)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= 4 * T) return;
+    const int64_t t = s >> 2;
+    const int a = (int)(s & 3);
+    const int64_t F = fa.F;
+    double d[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 12; k++) {
+        const int64_t f = t * 12 + k;
+        const int32_t rc = fa.rec[f];
+        const int aI = (rc >> 28) & 3, aJ = (rc >> 30) & 3;
+        if (aI != a && aJ != a) continue;
+        const R* fr = fa.frame + (int64_t)(rc & 0x0fffffff) * 8;
+        const double n[3] = {(double)fr[0], (double)fr[1], (double)fr[2]};
+        const double len = (double)fr[6];
+        double c[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) c[i] = (double)fa.cI[i * F + f];
+        if (aJ == a)
+#pragma unroll
+            for (int i = 0; i < 3; i++) c[i] -= len * n[i];
+        const double w = (double)fa.area[f] / len;
+        // translations: b = -+ e_i
+#pragma unroll
+        for (int i = 0; i < 3; i++) d[i] += w * E0 * (alpha + (1.0 - alpha) * n[i] * n[i]);
+        // rotations: b = +- c x e_i
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            double b[3] = {0, 0, 0};
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+            b[i1] = c[i2];   // (c x e_i)_{i+1} = c_{i+2}
+            b[i2] = -c[i1];  // (c x e_i)_{i+2} = -c_{i+1}
+            const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+            const double nb = n[0] * b[0] + n[1] * b[1] + n[2] * b[2];
+            d[3 + i] += w * E0 * (alpha * bb + (1.0 - alpha) * nb * nb);
+        }
+    }
+    const int64_t o = (int64_t)pos[s] * 6;
+#pragma unroll
+    for (int i = 0; i < 6; i++) out[o + i] = d[i];
+}
+
+// applied generalised forces of the free DoFs at `time` (zero on prescribed
+// DoFs), and prescribed velocities at `time_mid` (zero on free DoFs)
+__global__ __launch_bounds__(256) void k_im_loads(const uint8_t* __restrict__ mode, const int32_t* __restrict__ prog,
+                                                  const double* __restrict__ scale, const double* __restrict__ body,
+                                                  ProgArgs pr, double time, double time_mid, int64_t n6,
+                                                  double* __restrict__ f, double* __restrict__ vp)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n6) return;
+    const int32_t pg = prog[i];
+    if (mode[i] == 0) {
+        double a = body ? body[i] : 0.0;
+        if (pg >= 0) a += scale[i] * prog_at(pr, pg, time);
+        f[i] = a;
+        if (vp) vp[i] = 0.0;
+    } else {
+        f[i] = 0.0;
+        if (vp) vp[i] = pg >= 0 ? scale[i] * prog_at(pr, pg, time_mid) : 0.0;
+    }
+}
+
+// node records of a trial configuration: q slot = q, v slot = q - q_n (the
+// facet kernel, launched with dt = 1, then takes e(q) - e(q_n) as the strain
+// increment from the committed history)
+__global__ __launch_bounds__(256) void k_im_nodes(double* __restrict__ node, const double* __restrict__ q,
+                                                  const double* __restrict__ qn, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * N) return;
+    const int64_t c = i / N, p = i - c * N;
+    node[p * 16 + c] = q[i];
+    node[p * 16 + 6 + c] = qn ? q[i] - qn[i] : 0.0;
+}
+
+// predictor: q = q_n + dt v_n + dt^2/2 a_n on free DoFs, q_n + dt v_P(t + dt/2)
+// on prescribed ones
+__global__ __launch_bounds__(256) void k_im_predict(const uint8_t* __restrict__ mode, const double* __restrict__ qn,
+                                                    const double* __restrict__ vn, const double* __restrict__ an,
+                                                    const double* __restrict__ vp, double dt, int64_t n6,
+                                                    double* __restrict__ q)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n6) return;
+    q[i] = mode[i] == 0 ? qn[i] + dt * vn[i] + 0.5 * dt * dt * an[i] : qn[i] + dt * vp[i];
+}
+
+struct ImArgs {
+    const uint8_t* __restrict__ mode;
+    const double* __restrict__ M;      // [6][N] lumped diagonal
+    const double *qn, *vn, *an, *gn, *fn, *f1;
+    double dt, alpha, beta, gamma;
+    int64_t N;
+};
+
+// a = (q - q_n - dt v_n - dt^2 (1/2 - beta) a_n) / (beta dt^2),
+// rhs = (1 + alpha)(g + f1) - alpha (g_n + f_n), R = rhs - M a on free DoFs;
+// block partials of |R_F|^2, |(M a)_F|^2, |rhs_F|^2
+__global__ __launch_bounds__(IM_THREADS) void k_im_residual(ImArgs ia, const double* __restrict__ q,
+                                                            const double* __restrict__ g, double* __restrict__ Rv,
+                                                            double* __restrict__ part)
+{
+    double rr = 0.0, mm = 0.0, hh = 0.0;
+    const int64_t n6 = 6 * ia.N;
+    const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
+    const double bdt2 = ia.beta * ia.dt * ia.dt;
+    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
+        const double base = ia.qn[i] + ia.dt * ia.vn[i] + ia.dt * ia.dt * (0.5 - ia.beta) * ia.an[i];
+        const double a = (q[i] - base) / bdt2;
+        const double rhs = (1.0 + ia.alpha) * (g[i] + ia.f1[i]) - ia.alpha * (ia.gn[i] + ia.fn[i]);
+        const double ma = ia.M[i] * a;
+        double r = 0.0;
+        if (ia.mode[i] == 0) {
+            r = rhs - ma;
+            rr += r * r;
+            mm += ma * ma;
+            hh += rhs * rhs;
+        }
+        Rv[i] = r;
+    }
+    block_sum3(rr, mm, hh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rr;
+        part[gridDim.x + blockIdx.x] = mm;
+        part[2 * gridDim.x + blockIdx.x] = hh;
+    }
+}
+
+// accept the step: a, v, reactions on prescribed DoFs, external work
+// (trapezoid of applied + reaction forces over q - q_n, per particle in DoF
+// order), kinetic energy, and the new committed vectors
+__global__ __launch_bounds__(256) void k_im_accept(ImArgs ia, const double* __restrict__ q,
+                                                   const double* __restrict__ g, double* __restrict__ fext,
+                                                   double* __restrict__ wext, double* __restrict__ wkin,
+                                                   double* __restrict__ node, double* __restrict__ qn_o,
+                                                   double* __restrict__ vn_o, double* __restrict__ an_o,
+                                                   double* __restrict__ gn_o, double* __restrict__ fn_o,
+                                                   int32_t* __restrict__ flag)
+{
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = ia.N;
+    if (I >= N) return;
+    const double bdt2 = ia.beta * ia.dt * ia.dt;
+    double dwe = 0.0, wk = 0.0;
+    bool bad = false;
+    for (int d = 0; d < 6; d++) {
+        const int64_t i = d * N + I;
+        const double qq = q[i];
+        const double base = ia.qn[i] + ia.dt * ia.vn[i] + ia.dt * ia.dt * (0.5 - ia.beta) * ia.an[i];
+        const double a = (qq - base) / bdt2;
+        const double v = ia.vn[i] + ia.dt * ((1.0 - ia.gamma) * ia.an[i] + ia.gamma * a);
+        const double rhs = (1.0 + ia.alpha) * (g[i] + ia.f1[i]) - ia.alpha * (ia.gn[i] + ia.fn[i]);
+        const double ma = ia.M[i] * a;
+        const double Ft = ia.mode[i] == 0 ? ia.f1[i] : ma - rhs;
+        dwe += 0.5 * (fext[i] + Ft) * (qq - ia.qn[i]);
+        wk += 0.5 * ia.M[i] * v * v;
+        fext[i] = Ft;
+        node[I * 16 + d] = qq;
+        node[I * 16 + 6 + d] = v;
+        qn_o[i] = qq;
+        vn_o[i] = v;
+        an_o[i] = a;
+        gn_o[i] = g[i];
+        fn_o[i] = ia.f1[i];
+        bad = bad || !isfinite(v);
+    }
+    wext[I] += dwe;
+    wkin[I] = wk;
+    if (bad) flag[0] = 1;
+}
+
+// q += x on free DoFs
+__global__ __launch_bounds__(256) void k_im_add(const uint8_t* __restrict__ mode, const double* __restrict__ x,
+                                                int64_t n6, double* __restrict__ q)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n6 && mode[i] == 0) q[i] += x[i];
+}
+
+// ---------------------------------------------------------------------------
+// conjugate gradients on K_eff = cM M + cK K0 over the free DoFs, Jacobi
+// preconditioner; K0 p = -gather(facet kernel of the elastic law at p)
+// scalars: sc[0] = r.z, sc[1] = alpha_cg, sc[2] = beta_cg, sc[3] = r.r
+// ---------------------------------------------------------------------------
+struct CgArgs {
+    const uint8_t* __restrict__ mode;
+    const double* __restrict__ M;
+    const double* __restrict__ diag;  // K_eff diagonal
+    double *x, *r, *z, *p, *Ap, *sc, *part;
+    double cM, cK;
+    int64_t N;
+};
+
+// x = 0, r = R, z = r / diag, p = z; node_p slots = p; partials r.z, r.r
+__global__ __launch_bounds__(IM_THREADS) void k_cg_init(CgArgs cg, const double* __restrict__ R,
+                                                        double* __restrict__ node_p)
+{
+    double rz = 0.0, rr = 0.0, zz = 0.0;
+    const int64_t n6 = 6 * cg.N;
+    const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
+    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
+        const bool fr = cg.mode[i] == 0;
+        const double r = fr ? R[i] : 0.0;
+        const double z = fr ? r / cg.diag[i] : 0.0;
+        cg.x[i] = 0.0;
+        cg.r[i] = r;
+        cg.z[i] = z;
+        cg.p[i] = z;
+        const int64_t c = i / cg.N, pI = i - c * cg.N;
+        node_p[pI * 16 + c] = z;
+        rz += r * z;
+        rr += r * r;
+    }
+    block_sum3(rz, rr, zz);
+    if (threadIdx.x == 0) {
+        cg.part[blockIdx.x] = rz;
+        cg.part[gridDim.x + blockIdx.x] = rr;
+        cg.part[2 * gridDim.x + blockIdx.x] = 0.0;
+    }
+}
+
+// Ap = cM M p - cK y (y = -K0 p from the gather) on free DoFs; partial p.Ap
+__global__ __launch_bounds__(IM_THREADS) void k_cg_apply(CgArgs cg, const double* __restrict__ y)
+{
+    double pap = 0.0, u0 = 0.0, u1 = 0.0;
+    const int64_t n6 = 6 * cg.N;
+    const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
+    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
+        const double ap = cg.mode[i] == 0 ? cg.cM * cg.M[i] * cg.p[i] - cg.cK * y[i] : 0.0;
+        cg.Ap[i] = ap;
+        pap += cg.p[i] * ap;
+    }
+    block_sum3(pap, u0, u1);
+    if (threadIdx.x == 0) {
+        cg.part[blockIdx.x] = pap;
+        cg.part[gridDim.x + blockIdx.x] = 0.0;
+        cg.part[2 * gridDim.x + blockIdx.x] = 0.0;
+    }
+}
+
+// sc[1] = sc[0] / sum(partials of p.Ap)
+__global__ __launch_bounds__(IM_THREADS) void k_cg_alpha(CgArgs cg, int G)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < G; i += IM_THREADS) a += cg.part[i];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) cg.sc[1] = a != 0.0 ? cg.sc[0] / a : 0.0;
+}
+
+// x += alpha p, r -= alpha Ap, z = r / diag; partials r.z, r.r
+__global__ __launch_bounds__(IM_THREADS) void k_cg_update(CgArgs cg)
+{
+    const double al = cg.sc[1];
+    double rz = 0.0, rr = 0.0, u = 0.0;
+    const int64_t n6 = 6 * cg.N;
+    const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
+    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
+        if (cg.mode[i] != 0) continue;
+        cg.x[i] += al * cg.p[i];
+        const double r = cg.r[i] - al * cg.Ap[i];
+        const double z = r / cg.diag[i];
+        cg.r[i] = r;
+        cg.z[i] = z;
+        rz += r * z;
+        rr += r * r;
+    }
+    block_sum3(rz, rr, u);
+    if (threadIdx.x == 0) {
+        cg.part[blockIdx.x] = rz;
+        cg.part[gridDim.x + blockIdx.x] = rr;
+        cg.part[2 * gridDim.x + blockIdx.x] = 0.0;
+    }
+}
+
+// sc[2] = rz_new / sc[0]; sc[0] = rz_new; sc[3] = r.r  (first: only store)
+__global__ __launch_bounds__(IM_THREADS) void k_cg_beta(CgArgs cg, int G, int first)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < G; i += IM_THREADS) {
+        a += cg.part[i];
+        b += cg.part[G + i];
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        cg.sc[2] = (!first && cg.sc[0] != 0.0) ? a / cg.sc[0] : 0.0;
+        cg.sc[0] = a;
+        cg.sc[3] = b;
+        if (first) cg.sc[4] = b;  // r.r of the right-hand side
+    }
+}
+
+// p = z + beta p (free DoFs), written also to the q slots of node_p
+__global__ __launch_bounds__(256) void k_cg_newp(CgArgs cg, double* __restrict__ node_p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * cg.N) return;
+    const double p = cg.mode[i] == 0 ? cg.z[i] + cg.sc[2] * cg.p[i] : 0.0;
+    cg.p[i] = p;
+    const int64_t c = i / cg.N, pI = i - c * cg.N;
+    node_p[pI * 16 + c] = p;
+}
+
+// q_n, v_n from the node records
+__global__ __launch_bounds__(256) void k_im_unpack(const double* __restrict__ node, int64_t N, double* __restrict__ q,
+                                                   double* __restrict__ v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * N) return;
+    const int64_t c = i / N, p = i - c * N;
+    q[i] = node[p * 16 + c];
+    v[i] = node[p * 16 + 6 + c];
+}
+
+// node records <- q, v
+__global__ __launch_bounds__(256) void k_im_pack(double* __restrict__ node, const double* __restrict__ q,
+                                                 const double* __restrict__ v, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * N) return;
+    const int64_t c = i / N, p = i - c * N;
+    node[p * 16 + c] = q[i];
+    node[p * 16 + 6 + c] = v[i];
+}
+
+// diag <- cM M + cK diag(K0)
+__global__ __launch_bounds__(256) void k_im_diag_eff(const double* __restrict__ M, int64_t n6, double cM, double cK,
+                                                     double* __restrict__ diag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n6) diag[i] = cM * M[i] + cK * diag[i];
+}
+
+// a_0 = (g_0 + f_0) / M on free DoFs, 0 on prescribed ones; g_n = g_0;
+// fext = f_0 on free DoFs, 0 on prescribed ones
+__global__ __launch_bounds__(256) void k_im_init_acc(ImArgs ia, const double* __restrict__ g, double* __restrict__ an,
+                                                     double* __restrict__ gn, double* __restrict__ fext)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * ia.N) return;
+    const bool fr = ia.mode[i] == 0;
+    an[i] = fr ? (g[i] + ia.fn[i]) / ia.M[i] : 0.0;
+    gn[i] = g[i];
+    fext[i] = fr ? ia.fn[i] : 0.0;
+}

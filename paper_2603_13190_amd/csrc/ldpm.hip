@@ -83,6 +83,7 @@ ldpm_status ldpm_fail(ldpm_status st, const char* fmt, ...)
 
 #include "step_kernels.hpp"
 #include "fields.hpp"
+#include "implicit.hpp"
 
 // ---------------------------------------------------------------------------
 // host side
@@ -125,6 +126,13 @@ struct ldpm_system {
     // e_V [T], jump work [T], per-specimen sums)
     std::vector<double> wpert;
     void* pt_mem = nullptr;
+    // implicit HHT-alpha integrator (device buffers allocated at its first call)
+    bool imp_on = false;
+    double imp_dt = 0.0, imp_alpha = 0.0;
+    void* im_mem = nullptr;
+    double *im_q, *im_qn, *im_vn, *im_an, *im_gn, *im_fn, *im_f1, *im_vp, *im_g, *im_R, *im_M, *im_diag, *im_y;
+    double *cg_x, *cg_r, *cg_z, *cg_p, *cg_Ap, *cg_sc, *cg_part, *im_red;
+    double *im_node_p, *im_ht_scr, *im_wint_scr, *im_con_scr, *im_ht_c, *im_hem_c, *im_wint_c;
 };
 
 namespace {
@@ -803,6 +811,7 @@ ldpm_status ldpm_step(ldpm_system* s, int64_t n_steps)
 {
     if (!s) return fail(LDPM_ERR_ARG, "null handle");
     if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
+    if (s->imp_on) return fail(LDPM_ERR_STATE, "the handle integrates implicitly (ldpm_implicit_step)");
     hipError_t e = run_steps(s, n_steps);
     if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return LDPM_OK;
@@ -908,7 +917,7 @@ ldpm_status ldpm_energy(ldpm_system* s, int32_t sp, ldpm_energies* o)
     const double src = o->W_ext + o->W_pert + o->W_kin0;
     o->err = std::fabs(src - o->W_int - o->W_kin) / std::max(std::fabs(src), 1e-300);
     o->step = s->step;
-    o->time = (double)(s->step > 0 ? s->step - 1 : 0) * s->dt;
+    o->time = s->imp_on ? (double)s->step * s->imp_dt : (double)(s->step > 0 ? s->step - 1 : 0) * s->dt;
     return st;
 }
 
@@ -1248,12 +1257,15 @@ ldpm_status ldpm_crack_opening(ldpm_system* s, double* w)
     NodeArgs na{s->tet, s->node, s->N, s->T};
     const double E0 = s->matd.E0, aE0 = s->matd.aE0;
     const int first = s->step == 0;
+    // explicit: the last law evaluation was at q^n - dt v^{n-1/2};
+    // implicit: at the committed q_n itself
+    const double dtl = s->imp_on ? 0.0 : s->dt;
     if (s->prec == LDPM_PREC_MIXED)
         hipLaunchKernelGGL(k_crack<float>, dim3(blocks_for(s->F, 256)), dim3(256), 0, s->stream, na,
-                           facet_args<float>(s), E0, aE0, s->dt, first, w);
+                           facet_args<float>(s), E0, aE0, dtl, first, w);
     else
         hipLaunchKernelGGL(k_crack<double>, dim3(blocks_for(s->F, 256)), dim3(256), 0, s->stream, na,
-                           facet_args<double>(s), E0, aE0, s->dt, first, w);
+                           facet_args<double>(s), E0, aE0, dtl, first, w);
     HIP_TRY(hipGetLastError());
     return LDPM_OK;
 }
@@ -1264,8 +1276,8 @@ ldpm_status ldpm_volumetric_strain(ldpm_system* s, double* ev)
     if (!on_device(ev, s->device))
         return fail(LDPM_ERR_ARG, "volumetric_strain: ev must be device memory of the handle's GPU");
     NodeArgs na{s->tet, s->node, s->N, s->T};
-    hipLaunchKernelGGL(k_volstrain, dim3(blocks_for(s->T, 256)), dim3(256), 0, s->stream, na, s->dt,
-                       (int)(s->step == 0), (const double*)nullptr, ev);
+    hipLaunchKernelGGL(k_volstrain, dim3(blocks_for(s->T, 256)), dim3(256), 0, s->stream, na,
+                       s->imp_on ? 0.0 : s->dt, (int)(s->step == 0), (const double*)nullptr, ev);
     HIP_TRY(hipGetLastError());
     return LDPM_OK;
 }
@@ -1317,6 +1329,7 @@ static void launch_jump(ldpm_system* s, const double* d, const double* evj, doub
 ldpm_status ldpm_perturb(ldpm_system* s, const double* delta, double* work)
 {
     if (!s || !delta) return fail(LDPM_ERR_ARG, "null argument");
+    if (s->imp_on) return fail(LDPM_ERR_STATE, "perturbations apply to explicit runs");
     const int64_t N = s->N, T = s->T;
     if (!finite_all(delta, 6 * N)) return fail(LDPM_ERR_ARG, "perturb: non-finite delta");
     Carve cv;
@@ -1362,6 +1375,287 @@ ldpm_status ldpm_perturb(ldpm_system* s, const double* delta, double* work)
     return LDPM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// implicit HHT-alpha integration (modified Newton on the initial elastic
+// stiffness, inner solves by Jacobi-preconditioned conjugate gradients with
+// the stiffness applied matrix-free by the facet kernel of the elastic law)
+// ---------------------------------------------------------------------------
+extern "C++" {
+namespace {
+unsigned im_blocks(int64_t n) { return (unsigned)std::min<int64_t>(IM_MAX_BLOCKS, (n + IM_THREADS - 1) / IM_THREADS); }
+
+template <int LAW, int TB>
+void launch_facet_plain(ldpm_system* s, const NodeArgs& na, const FacetArgs<double>& fa, double* contrib,
+                        double* wint, const ProgArgs& pr, int64_t step, double dt)
+{
+    const MatDev<double>& mat = s->matd;
+    const int64_t nb = (s->T + TB - 1) / TB;
+    hipLaunchKernelGGL((k_facet<double, LAW, TB, MODE_PLAIN>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na,
+                       fa, mat, (const int32_t*)s->pos, contrib, wint, pr, step, dt, s->launch.xcd_remap,
+                       SurrogateArgs{}, CaptureArgs{});
+}
+
+template <int LAW>
+void launch_facet_plain_l(ldpm_system* s, const NodeArgs& na, const FacetArgs<double>& fa, double* contrib,
+                          double* wint, const ProgArgs& pr, int64_t step, double dt)
+{
+    switch (s->launch.tets_per_block) {
+    case 8: launch_facet_plain<LAW, 8>(s, na, fa, contrib, wint, pr, step, dt); break;
+    case 32: launch_facet_plain<LAW, 32>(s, na, fa, contrib, wint, pr, step, dt); break;
+    case 64: launch_facet_plain<LAW, 64>(s, na, fa, contrib, wint, pr, step, dt); break;
+    default: launch_facet_plain<LAW, 16>(s, na, fa, contrib, wint, pr, step, dt); break;
+    }
+}
+
+hipError_t im_alloc(ldpm_system* s)
+{
+    const int64_t N = s->N, T = s->T, F = s->F;
+    const int G = (int)im_blocks(6 * N);
+    Carve cv;
+    const size_t n6 = 6 * N;
+    size_t o[32];
+    int k = 0;
+    for (int i = 0; i < 13; i++) o[k++] = cv.take<double>(n6);     // im_* vectors
+    for (int i = 0; i < 5; i++) o[k++] = cv.take<double>(n6);      // cg x r z p Ap
+    o[k++] = cv.take<double>(8);                                    // cg_sc
+    o[k++] = cv.take<double>(3 * (size_t)G);                        // cg_part
+    o[k++] = cv.take<double>(8);                                    // im_red
+    o[k++] = cv.take<double>(16 * N);                               // node_p
+    o[k++] = cv.take<double>(3 * F);                                // ht scratch
+    o[k++] = cv.take<double>(T);                                    // wint scratch
+    o[k++] = cv.take<double>(24 * T);                               // contrib scratch
+    o[k++] = cv.take<double>(3 * F);                                // committed history copies
+    o[k++] = cv.take<double>(F);
+    o[k++] = cv.take<double>(T);
+    const size_t bytes = (cv.off + 255) & ~size_t(255);
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, bytes);
+    if (e != hipSuccess) return e;
+    s->im_mem = mem;
+    char* B = (char*)mem;
+    double** vec[13] = {&s->im_q, &s->im_qn, &s->im_vn, &s->im_an, &s->im_gn, &s->im_fn, &s->im_f1,
+                        &s->im_vp, &s->im_g, &s->im_R, &s->im_M, &s->im_diag, &s->im_y};
+    k = 0;
+    for (int i = 0; i < 13; i++) *vec[i] = (double*)(B + o[k++]);
+    double** cgv[5] = {&s->cg_x, &s->cg_r, &s->cg_z, &s->cg_p, &s->cg_Ap};
+    for (int i = 0; i < 5; i++) *cgv[i] = (double*)(B + o[k++]);
+    s->cg_sc = (double*)(B + o[k++]);
+    s->cg_part = (double*)(B + o[k++]);
+    s->im_red = (double*)(B + o[k++]);
+    s->im_node_p = (double*)(B + o[k++]);
+    s->im_ht_scr = (double*)(B + o[k++]);
+    s->im_wint_scr = (double*)(B + o[k++]);
+    s->im_con_scr = (double*)(B + o[k++]);
+    s->im_ht_c = (double*)(B + o[k++]);
+    s->im_hem_c = (double*)(B + o[k++]);
+    s->im_wint_c = (double*)(B + o[k++]);
+    return hipSuccess;
+}
+
+ProgArgs prog_args(ldpm_system* s) { return ProgArgs{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog}; }
+
+// g = -f_int(q) from the committed history: trial node records, history
+// restored from the committed copies, facet kernel (dt = 1: the strain
+// increment is e(q) - e(q_n); first: from the undeformed state), gather
+hipError_t im_trial(ldpm_system* s, const double* q, int first)
+{
+    const int64_t N = s->N, T = s->T, F = s->F;
+    hipLaunchKernelGGL(k_im_nodes, dim3(blocks_for(6 * N, 256)), dim3(256), 0, s->stream, s->node, q,
+                       (const double*)s->im_qn, N);
+    hipError_t e = hipMemcpyAsync(s->ht, s->im_ht_c, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && s->law != 0)
+        e = hipMemcpyAsync(s->hemax, s->im_hem_c, F * 8, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->wint, s->im_wint_c, T * 8, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return e;
+    NodeArgs na{s->tet, s->node, N, T};
+    const FacetArgs<double> fa = facet_args<double>(s);
+    const ProgArgs pr = prog_args(s);
+    if (s->law == 0) launch_facet_plain_l<0>(s, na, fa, (double*)s->contrib, s->wint, pr, first ? 0 : 1, 1.0);
+    else launch_facet_plain_l<1>(s, na, fa, (double*)s->contrib, s->wint, pr, first ? 0 : 1, 1.0);
+    hipLaunchKernelGGL(k_im_gather<double>, dim3(blocks_for(N * PG, 256)), dim3(256), 0, s->stream,
+                       (const int32_t*)s->ptr, (const double*)s->contrib, N, s->im_g);
+    return hipGetLastError();
+}
+
+// y = -K0 p for the p in the q slots of node_p (elastic law on scratch history)
+void im_k0_apply(ldpm_system* s)
+{
+    NodeArgs na{s->tet, s->im_node_p, s->N, s->T};
+    FacetArgs<double> fa = facet_args<double>(s);
+    fa.ht = s->im_ht_scr;
+    fa.hemax = nullptr;
+    const ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, 0};
+    launch_facet_plain_l<0>(s, na, fa, s->im_con_scr, s->im_wint_scr, pr, 1, 1.0);
+    hipLaunchKernelGGL(k_im_gather<double>, dim3(blocks_for(s->N * PG, 256)), dim3(256), 0, s->stream,
+                       (const int32_t*)s->ptr, (const double*)s->im_con_scr, s->N, s->im_y);
+}
+
+// x = K_eff^{-1} R on the free DoFs; returns the iterations
+hipError_t im_cg(ldpm_system* s, double cM, double cK, double tol, int max_it, int* its)
+{
+    const int64_t N = s->N;
+    const int G = (int)im_blocks(6 * N);
+    CgArgs cg{s->mode, s->im_M, s->im_diag, s->cg_x, s->cg_r, s->cg_z, s->cg_p, s->cg_Ap, s->cg_sc, s->cg_part,
+              cM, cK, N};
+    hipLaunchKernelGGL(k_cg_init, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)s->im_R, s->im_node_p);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, G, 1);
+    double sc[8];
+    hipError_t e = hipMemcpyAsync(sc, s->cg_sc, 64, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return e;
+    const double rr0 = sc[4];
+    int it = 0;
+    if (rr0 > 0.0) {
+        while (it < max_it) {
+            im_k0_apply(s);
+            hipLaunchKernelGGL(k_cg_apply, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)s->im_y);
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, G);
+            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(IM_THREADS), 0, s->stream, cg);
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, G, 0);
+            it++;
+            if (it % 8 == 0 || it == max_it) {
+                e = hipMemcpyAsync(sc, s->cg_sc, 64, hipMemcpyDeviceToHost, s->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+                if (e != hipSuccess) return e;
+                if (!(sc[3] > tol * tol * rr0)) break;
+            }
+            hipLaunchKernelGGL(k_cg_newp, dim3(blocks_for(6 * N, 256)), dim3(256), 0, s->stream, cg, s->im_node_p);
+        }
+    }
+    *its = it;
+    return hipGetLastError();
+}
+
+// |R_F|, |(M a)_F| + |rhs_F| of the trial q
+hipError_t im_residual(ldpm_system* s, const ImArgs& ia, double* res, double* ref)
+{
+    const int G = (int)im_blocks(6 * s->N);
+    hipLaunchKernelGGL(k_im_residual, dim3(G), dim3(IM_THREADS), 0, s->stream, ia, (const double*)s->im_q,
+                       (const double*)s->im_g, s->im_R, s->cg_part);
+    hipLaunchKernelGGL(k_im_reduce3, dim3(1), dim3(IM_THREADS), 0, s->stream, (const double*)s->cg_part, G, s->im_red);
+    double r[3];
+    hipError_t e = hipMemcpyAsync(r, s->im_red, 24, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    *res = std::sqrt(r[0]);
+    *ref = std::sqrt(r[1]) + std::sqrt(r[2]);
+    return e;
+}
+}  // namespace
+}  // extern "C++"
+
+ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int64_t n_steps,
+                               ldpm_implicit_stats* stats)
+{
+    if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
+    if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
+    if (s->prec != LDPM_PREC_FP64) return fail(LDPM_ERR_ARG, "the implicit integrator runs in FP64 only");
+    if (s->mblk) return fail(LDPM_ERR_ARG, "the implicit integrator takes the lumped diagonal mass only");
+    if (s->sg_on || s->cp_on) return fail(LDPM_ERR_STATE, "surrogate or capture active");
+    if (!(o->dt > 0) || !std::isfinite(o->dt)) return fail(LDPM_ERR_ARG, "implicit dt must be positive");
+    if (!(o->alpha >= -1.0 / 3.0 - 1e-15 && o->alpha <= 0.0)) return fail(LDPM_ERR_ARG, "alpha must lie in [-1/3, 0]");
+    if (!(o->tol > 0) || o->max_iter < 1 || !(o->cg_tol > 0) || o->cg_max_iter < 1)
+        return fail(LDPM_ERR_ARG, "tolerances and iteration limits must be positive");
+    if (!s->imp_on && s->step > 0) return fail(LDPM_ERR_STATE, "explicit steps were taken on this handle");
+    if (s->imp_on && (o->dt != s->imp_dt || o->alpha != s->imp_alpha))
+        return fail(LDPM_ERR_ARG, "dt and alpha are fixed after the first implicit step");
+    const int64_t N = s->N, T = s->T, F = s->F;
+    const double dt = o->dt, al = o->alpha, be = (1.0 - al) * (1.0 - al) / 4.0, ga = 0.5 - al;
+    const double cM = 1.0 / (be * dt * dt), cK = 1.0 + al;
+    hipError_t e = hipSuccess;
+    if (!s->im_mem) {
+        e = im_alloc(s);
+        if (e != hipSuccess) return fail(LDPM_ERR_ALLOC, "implicit: device allocation failed: %s", hipGetErrorString(e));
+    }
+    const int64_t n6 = 6 * N;
+    const unsigned b6 = blocks_for(n6, 256);
+    ImArgs ia{s->mode, s->im_M, s->im_qn, s->im_vn, s->im_an, s->im_gn, s->im_fn, s->im_f1, dt, al, be, ga, N};
+    if (!s->imp_on) {
+        // committed state from the node records, lumped masses, K_eff diagonal
+        hipLaunchKernelGGL(k_im_unpack, dim3(b6), dim3(256), 0, s->stream, (const double*)s->node, N, s->im_qn, s->im_vn);
+        for (int d = 0; d < 3; d++) HIP_TRY(hipMemcpyAsync(s->im_M + d * N, s->mass, N * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->im_M + 3 * N, s->inertia, 3 * N * 8, hipMemcpyDeviceToDevice, s->stream));
+        hipLaunchKernelGGL(k_im_diag_k0<double>, dim3(blocks_for(4 * T, 256)), dim3(256), 0, s->stream,
+                           facet_args<double>(s), (const int32_t*)s->pos, T, s->matd.E0, s->matd.alpha, s->im_con_scr);
+        hipLaunchKernelGGL(k_im_gather<double>, dim3(blocks_for(N * PG, 256)), dim3(256), 0, s->stream,
+                           (const int32_t*)s->ptr, (const double*)s->im_con_scr, N, s->im_diag);
+        hipLaunchKernelGGL(k_im_diag_eff, dim3(b6), dim3(256), 0, s->stream, (const double*)s->im_M, n6, cM, cK,
+                           s->im_diag);
+        HIP_TRY(hipMemcpyAsync(s->im_node_p, s->node, 16 * N * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemsetAsync(s->cg_Ap, 0, n6 * 8, s->stream));
+        hipLaunchKernelGGL(k_im_nodes, dim3(b6), dim3(256), 0, s->stream, s->im_node_p, (const double*)s->cg_Ap, nullptr, N);
+        HIP_TRY(hipMemsetAsync(s->im_ht_scr, 0, 3 * F * 8, s->stream));
+        HIP_TRY(hipMemsetAsync(s->im_wint_scr, 0, T * 8, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->im_ht_c, s->ht, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream));
+        if (s->law != 0) HIP_TRY(hipMemcpyAsync(s->im_hem_c, s->hemax, F * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->im_wint_c, s->wint, T * 8, hipMemcpyDeviceToDevice, s->stream));
+        // a_0 from M a_0 = g(q_0) + f(0) on the free DoFs
+        e = im_trial(s, s->im_qn, s->step == 0);
+        if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "implicit: %s", hipGetErrorString(e));
+        const ProgArgs pr = prog_args(s);
+        const double t0 = (double)s->step * dt;
+        hipLaunchKernelGGL(k_im_loads, dim3(b6), dim3(256), 0, s->stream, s->mode, s->prog, s->scale,
+                           (const double*)s->body, pr, t0, t0, n6, s->im_fn, (double*)nullptr);
+        hipLaunchKernelGGL(k_im_init_acc, dim3(b6), dim3(256), 0, s->stream, ia, (const double*)s->im_g, s->im_an,
+                           s->im_gn, s->fext);
+        HIP_TRY(hipGetLastError());
+        // the trial left its history in place: back to the committed one
+        HIP_TRY(hipMemcpyAsync(s->ht, s->im_ht_c, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream));
+        if (s->law != 0) HIP_TRY(hipMemcpyAsync(s->hemax, s->im_hem_c, F * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->wint, s->im_wint_c, T * 8, hipMemcpyDeviceToDevice, s->stream));
+        hipLaunchKernelGGL(k_im_pack, dim3(b6), dim3(256), 0, s->stream, s->node, (const double*)s->im_qn,
+                           (const double*)s->im_vn, N);
+        s->imp_on = true;
+        s->imp_dt = dt;
+        s->imp_alpha = al;
+    }
+    int64_t newton = 0, cgits = 0, notconv = 0;
+    double maxres = 0.0;
+    const ProgArgs pr = prog_args(s);
+    for (int64_t it = 0; it < n_steps; it++) {
+        const double tn = (double)s->step * dt;
+        const int first = s->step == 0;
+        hipLaunchKernelGGL(k_im_loads, dim3(b6), dim3(256), 0, s->stream, s->mode, s->prog, s->scale,
+                           (const double*)s->body, pr, tn + dt, tn + 0.5 * dt, n6, s->im_f1, s->im_vp);
+        hipLaunchKernelGGL(k_im_predict, dim3(b6), dim3(256), 0, s->stream, s->mode, (const double*)s->im_qn,
+                           (const double*)s->im_vn, (const double*)s->im_an, (const double*)s->im_vp, dt, n6, s->im_q);
+        int k = 0;
+        double res = 0.0, ref = 0.0;
+        while (true) {
+            e = im_trial(s, s->im_q, first);
+            if (e == hipSuccess) e = im_residual(s, ia, &res, &ref);
+            if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "implicit: %s", hipGetErrorString(e));
+            if (!std::isfinite(res)) return fail(LDPM_ERR_UNSTABLE, "implicit: non-finite residual");
+            if (res <= o->tol * ref || k == o->max_iter) break;
+            int its = 0;
+            e = im_cg(s, cM, cK, o->cg_tol, o->cg_max_iter, &its);
+            if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "implicit CG: %s", hipGetErrorString(e));
+            cgits += its;
+            hipLaunchKernelGGL(k_im_add, dim3(b6), dim3(256), 0, s->stream, s->mode, (const double*)s->cg_x, n6, s->im_q);
+            k++;
+        }
+        newton += k;
+        const double rel = ref > 0 ? res / ref : 0.0;
+        if (!(res <= o->tol * ref)) notconv++;
+        maxres = std::max(maxres, rel);
+        hipLaunchKernelGGL(k_im_accept, dim3(blocks_for(N, 256)), dim3(256), 0, s->stream, ia, (const double*)s->im_q,
+                           (const double*)s->im_g, s->fext, s->wext, s->wkin, s->node, s->im_qn, s->im_vn, s->im_an,
+                           s->im_gn, s->im_fn, s->flag);
+        HIP_TRY(hipMemcpyAsync(s->im_ht_c, s->ht, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream));
+        if (s->law != 0) HIP_TRY(hipMemcpyAsync(s->im_hem_c, s->hemax, F * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->im_wint_c, s->wint, T * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipGetLastError());
+        s->step++;
+    }
+    if (stats) {
+        stats->steps = n_steps;
+        stats->newton_iters = newton;
+        stats->cg_iters = cgits;
+        stats->not_converged = notconv;
+        stats->max_residual = maxres;
+    }
+    return ldpm_sync(s);
+}
+
 ldpm_status ldpm_get_launch(ldpm_system* s, ldpm_launch* o)
 {
     if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
@@ -1376,6 +1670,7 @@ void ldpm_free(ldpm_system* s)
     if (s->sg_mem) (void)hipFree(s->sg_mem);
     if (s->cp_mem) (void)hipFree(s->cp_mem);
     if (s->pt_mem) (void)hipFree(s->pt_mem);
+    if (s->im_mem) (void)hipFree(s->im_mem);
     if (s->arena) {
         (void)hipStreamSynchronize(s->stream);
         if (s->dev_free) s->dev_free(s->arena, s->alloc_ctx);

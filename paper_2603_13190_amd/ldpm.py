@@ -26,7 +26,7 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
            "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_capture_begin",
            "ldpm_capture_end", "ldpm_crack_opening", "ldpm_volumetric_strain", "ldpm_compare_fields",
-           "ldpm_perturb",
+           "ldpm_perturb", "ldpm_implicit_step",
            "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
@@ -111,6 +111,16 @@ class FieldStats(C.Structure):
                 ("nrmse", C.c_double)]
 
 
+class ImplicitOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("alpha", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32)]
+
+
+class ImplicitStats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("newton_iters", C.c_int64), ("cg_iters", C.c_int64),
+                ("not_converged", C.c_int64), ("max_residual", C.c_double)]
+
+
 class LdpmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"ldpm {_STATUS.get(status, status)}: {msg}")
@@ -161,6 +171,8 @@ def lib():
         L.ldpm_compare_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
                                           C.POINTER(FieldStats)]
         L.ldpm_perturb.argtypes = [C.c_void_p, _dp, _dp]
+        L.ldpm_implicit_step.argtypes = [C.c_void_p, C.POINTER(ImplicitOpts), C.c_int64,
+                                         C.POINTER(ImplicitStats)]
         L.ldpm_free.argtypes = [C.c_void_p]
         L.ldpm_free.restype = None
         L.ldpm_last_error.restype = C.c_char_p
@@ -495,6 +507,13 @@ class System:
         _check(lib().ldpm_perturb(self.h, _p(d, _dp), C.byref(w)))
         return float(w.value)
 
+    def implicit_step(self, n, dt, alpha=0.0, tol=1e-8, max_iter=100, cg_tol=1e-10, cg_max_iter=5000):
+        """n implicit HHT-alpha steps; returns the iteration statistics."""
+        o = ImplicitOpts(float(dt), float(alpha), float(tol), int(max_iter), float(cg_tol), int(cg_max_iter))
+        st = ImplicitStats()
+        _check(lib().ldpm_implicit_step(self.h, C.byref(o), int(n), C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ImplicitStats._fields_}
+
     def close(self):
         if getattr(self, "h", None):
             lib().ldpm_free(self.h)
@@ -604,6 +623,13 @@ class Mlp:
         w = C.c_double()
         _check(lib().ldpm_perturb(self.h, _p(d, _dp), C.byref(w)))
         return float(w.value)
+
+    def implicit_step(self, n, dt, alpha=0.0, tol=1e-8, max_iter=100, cg_tol=1e-10, cg_max_iter=5000):
+        """n implicit HHT-alpha steps; returns the iteration statistics."""
+        o = ImplicitOpts(float(dt), float(alpha), float(tol), int(max_iter), float(cg_tol), int(cg_max_iter))
+        st = ImplicitStats()
+        _check(lib().ldpm_implicit_step(self.h, C.byref(o), int(n), C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ImplicitStats._fields_}
 
     def close(self):
         if getattr(self, "h", None):
