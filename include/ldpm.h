@@ -399,35 +399,42 @@ ldpm_status ldpm_compare_fields(const double *x, const double *ref, int64_t n, d
  * Explicit runs only (LDPM_ERR_STATE after implicit steps).               */
 ldpm_status ldpm_perturb(ldpm_system *s, const double *delta, double *work);
 
-/* ---- Implicit HHT-alpha integration --------------------------------------
+/* ---- Implicit generalised-alpha / HHT-alpha integration ------------------
  * The paper's implicit solvers integrate the same equations with the HHT
  * (Hilber-Hughes-Taylor) alpha or generalised-alpha methods and Newton-type
- * iterations.  ldpm_implicit_step advances n_steps steps of the HHT-alpha
- * method (beta = (1 - alpha)^2 / 4, gamma = 1/2 - alpha):
- *   M a_{n+1} = (1 + alpha)(g(q_{n+1}) + f_{n+1}) - alpha (g(q_n) + f_n) + R_{n+1},
+ * iterations.  ldpm_implicit_step advances n_steps steps of the
+ * generalised-alpha family with interpolated forces:
+ *   (1 - a_m) M a_{n+1} + a_m M a_n
+ *       = (1 - a_f)(g(q_{n+1}) + f_{n+1}) + a_f (g(q_n) + f_n) + R_{n+1},
  *   q_{n+1} = q_n + dt v_n + dt^2 ((1/2 - beta) a_n + beta a_{n+1}),
  *   v_{n+1} = v_n + dt ((1 - gamma) a_n + gamma a_{n+1}),
+ *   gamma = 1/2 - a_m + a_f, beta = (1 - a_m + a_f)^2 / 4,
+ * with a_m = alpha_m, a_f = alpha_f.  HHT-alpha is a_m = 0, a_f = -alpha
+ * (alpha in [-1/3, 0]; 0: the trapezoidal rule); the generalised-alpha
+ * method with high-frequency spectral radius rho in [0, 1] is
+ * a_m = (2 rho - 1)/(rho + 1), a_f = rho/(rho + 1).
  * g = -f_int (the gathered facet forces), f the applied forces, R the
  * reactions of prescribed DoFs, which move by dt v_P(t_n + dt/2).  Each step
  * is solved by modified Newton on the free DoFs with the initial elastic
- * stiffness K0: K_eff = M / (beta dt^2) + (1 + alpha) K0, its systems solved
- * by Jacobi-preconditioned conjugate gradients with K0 applied matrix-free
- * (the facet kernel of the elastic law).  Every Newton iteration evaluates
- * the facet law at the trial configuration from the committed history; the
- * last trial is committed when the step is accepted: when
- * |R_F|_2 <= tol (|(M a)_F|_2 + |rhs_F|_2) or after max_iter iterations
- * (counted in not_converged).  The predictor keeps the acceleration.
- * The state then holds q_n, v_n (not the explicit scheme's mid-step
- * velocities): a handle integrates either explicitly or implicitly
- * (LDPM_ERR_STATE otherwise), and dt and alpha stay fixed after the first
- * implicit step.  FP64, lumped mass, no surrogate or capture.  Energies as
- * for the explicit step (W_int facet trapezoids of accepted steps, W_ext the
- * trapezoid of applied + reaction forces, W_kin = 1/2 v^T M v) at
- * t_n = n dt.  The first call allocates device buffers of about
- * 8 (120 N + 7 F + 26 T) bytes, kept by the handle.  Synchronises.          */
+ * stiffness K0: K_eff = (1 - a_m) M / (beta dt^2) + (1 - a_f) K0, its systems
+ * solved by Jacobi-preconditioned conjugate gradients with K0 applied
+ * matrix-free (the facet kernel of the elastic law).  Every Newton iteration
+ * evaluates the facet law at the trial configuration from the committed
+ * history; the last trial is committed when the step is accepted: when
+ * |R_F|_2 <= tol (|((1 - a_m) M a)_F|_2 + |rhs_F|_2) or after max_iter
+ * iterations (counted in not_converged).  The predictor keeps the
+ * acceleration.  The state then holds q_n, v_n (not the explicit scheme's
+ * mid-step velocities): a handle integrates either explicitly or implicitly
+ * (LDPM_ERR_STATE otherwise), and dt, alpha_m, alpha_f stay fixed after the
+ * first implicit step.  FP64, lumped mass, no surrogate or capture.
+ * Energies as for the explicit step (W_int facet trapezoids of accepted
+ * steps, W_ext the trapezoid of applied + reaction forces, W_kin =
+ * 1/2 v^T M v) at t_n = n dt.  The first call allocates device buffers of
+ * about 8 (120 N + 7 F + 26 T) bytes, kept by the handle.  Synchronises.   */
 typedef struct {
     double dt;           /* implicit time step (> 0) */
-    double alpha;        /* HHT alpha in [-1/3, 0] (0: trapezoidal rule) */
+    double alpha_m;      /* >= -1 (HHT: 0) */
+    double alpha_f;      /* alpha_m <= alpha_f <= 1/2 (HHT: -alpha) */
     double tol;          /* relative Newton tolerance (> 0) */
     int32_t max_iter;    /* Newton iterations per step (>= 1) */
     double cg_tol;       /* relative residual of the CG solves (> 0) */

@@ -6,18 +6,24 @@ benchmark, never by the solver package.
 The paper's implicit solvers integrate M q'' + f_int(q) = f_ext with the
 HHT (Hilber-Hughes-Taylor) alpha method or the generalised-alpha method and
 Newton-type iterations (sections on the implementations and on the
-time-integration schemes).  This module writes out the HHT-alpha method:
+time-integration schemes).  This module writes out the generalised-alpha
+family with interpolated forces (Chung and Hulbert's parameters), of which
+HHT-alpha is the member alpha_m = 0, alpha_f = -alpha:
 
-  M a_{n+1} = (1 + alpha) (g(q_{n+1}) + f_{n+1}) - alpha (g(q_n) + f_n) + R_{n+1},
+  (1 - a_m) M a_{n+1} + a_m M a_n
+      = (1 - a_f) (g(q_{n+1}) + f_{n+1}) + a_f (g(q_n) + f_n) + R_{n+1},
   q_{n+1} = q_n + dt v_n + dt^2 ((1/2 - beta) a_n + beta a_{n+1}),
   v_{n+1} = v_n + dt ((1 - gamma) a_n + gamma a_{n+1}),
-  beta = (1 - alpha)^2 / 4, gamma = 1/2 - alpha, alpha in [-1/3, 0],
+  gamma = 1/2 - a_m + a_f, beta = (1 - a_m + a_f)^2 / 4;
+  HHT: a_m = 0, a_f = -alpha, alpha in [-1/3, 0];
+  generalised-alpha from the high-frequency spectral radius rho_inf in
+  [0, 1]: a_m = (2 rho_inf - 1) / (rho_inf + 1), a_f = rho_inf / (rho_inf + 1),
 
 with g = -f_int (the facet forces gathered as in the explicit step), f the
 applied forces, and R the reactions of prescribed DoFs.  Each step is
 solved by modified Newton on the free DoFs with the initial elastic
-stiffness K0: K_eff = M / (beta dt^2) + (1 + alpha) K0, factorised once
-(scipy sparse LU).  The facet laws are evaluated from the committed history
+stiffness K0: K_eff = (1 - a_m) M / (beta dt^2) + (1 - a_f) K0, factorised
+once (scipy sparse LU).  The facet laws are evaluated from the committed history
 at every trial configuration and committed when the step is accepted.
 
 Readings (the paper does not write these out):
@@ -25,9 +31,11 @@ Readings (the paper does not write these out):
   q_{n+1,P} = q_{n,P} + dt v_P(t_n + dt/2), and take a, v from the Newmark
   relations;
 - the predictor keeps the acceleration, a^(0)_{n+1} = a_n;
-- a step is accepted when ||R_F||_2 <= tol (||(M a)_F||_2 + ||rhs_F||_2),
-  rhs the right-hand side above, or after max_iter iterations (the paper's
-  runs accept non-converged steps after a fixed number of iterations);
+- a step is accepted when ||R_F||_2 <= tol (||((1 - a_m) M a)_F||_2 +
+  ||rhs_F||_2), rhs the other terms above, or after max_iter iterations
+  (the paper's runs accept non-converged steps after a fixed number of
+  iterations);
+- reactions of prescribed DoFs: R = (1 - a_m) M a_{n+1} - rhs;
 - a_0 solves M a_0 = g(q_0) + f(0) on the free DoFs (zero on prescribed);
 - energies: W_int from the facet trapezoids of the accepted steps, W_kin =
   1/2 v^T M v, W_ext the trapezoid of (applied + reaction) forces over the
@@ -80,17 +88,28 @@ def elastic_stiffness(sysd):
     return K
 
 
-class HHT:
-    """HHT-alpha integrator on an Oracle's state (q, v are q_n, v_n)."""
+def gen_alpha_params(rho_inf):
+    """(alpha_m, alpha_f) of the generalised-alpha method for rho_inf."""
+    r = float(rho_inf)
+    return (2.0 * r - 1.0) / (r + 1.0), r / (r + 1.0)
 
-    def __init__(self, o: Oracle, sysd, dt, alpha=0.0, tol=1e-10, max_iter=100):
+
+class HHT:
+    """Generalised-alpha / HHT-alpha integrator on an Oracle's state (q, v
+    are q_n, v_n).  alpha: HHT's alpha (alpha_f = -alpha) unless alpha_f is
+    given; alpha_m = 0 is HHT."""
+
+    def __init__(self, o: Oracle, sysd, dt, alpha=0.0, tol=1e-10, max_iter=100, alpha_m=0.0, alpha_f=None):
         if sysd.get("mass_block") is not None:
             raise ValueError("the implicit oracle takes the lumped diagonal mass only")
-        if not (-1.0 / 3.0 - 1e-15 <= alpha <= 0.0):
-            raise ValueError("alpha must lie in [-1/3, 0]")
-        self.o, self.dt, self.alpha = o, float(dt), float(alpha)
-        self.beta = (1.0 - alpha) ** 2 / 4.0
-        self.gamma = 0.5 - alpha
+        am = float(alpha_m)
+        af = -float(alpha) if alpha_f is None else float(alpha_f)
+        if not (am <= af + 1e-15 and af <= 0.5 + 1e-15 and am >= -1.0):
+            raise ValueError("need alpha_m <= alpha_f <= 1/2")
+        self.o, self.dt = o, float(dt)
+        self.am, self.af = am, af
+        self.gamma = 0.5 - am + af
+        self.beta = (1.0 - am + af) ** 2 / 4.0
         self.tol, self.max_iter = float(tol), int(max_iter)
         N = o.N
         self.M = np.concatenate([np.repeat(np.asarray(sysd["mass"])[:, None], 3, 1),
@@ -111,7 +130,7 @@ class HHT:
         K0 = elastic_stiffness(sysd)
         fr = np.flatnonzero(self.free.ravel())
         self.fr = fr
-        Keff = sp.diags(self.M.ravel()[fr] / (self.beta * self.dt ** 2)) + (1.0 + alpha) * K0[fr][:, fr]
+        Keff = sp.diags((1.0 - am) * self.M.ravel()[fr] / (self.beta * self.dt ** 2)) + (1.0 - af) * K0[fr][:, fr]
         self.lu = sla.splu(Keff.tocsc())
         self.a = None
         self.g_n = None
@@ -160,7 +179,7 @@ class HHT:
 
     # -- steps ----------------------------------------------------------
     def step(self, n=1):
-        o, dt, al, be, ga = self.o, self.dt, self.alpha, self.beta, self.gamma
+        o, dt, am, af, be, ga = self.o, self.dt, self.am, self.af, self.beta, self.gamma
         M, free = self.M, self.free
         for _ in range(n):
             tn = o.step_index * dt
@@ -182,8 +201,8 @@ class HHT:
             while True:
                 a = (q - base) / (be * dt * dt)
                 g, t, e, em, dW = self.trial(q)
-                rhs = (1.0 + al) * (g + f1) - al * (self.g_n + self.f_n)
-                Ma = M * a
+                rhs = (1.0 - af) * (g + f1) + af * (self.g_n + self.f_n) - am * M * an
+                Ma = (1.0 - am) * M * a
                 Rf = (rhs - Ma)[free]
                 ref = np.linalg.norm(Ma[free]) + np.linalg.norm(rhs[free])
                 res = np.linalg.norm(Rf)

@@ -1,4 +1,4 @@
-// Device side of the implicit HHT-alpha integrator: per-DoF vector kernels,
+// Device side of the implicit generalised-alpha / HHT-alpha integrator: per-DoF vector kernels,
 // the deterministic gather of tet-node records into particle vectors, the
 // diagonal of the initial elastic stiffness, and the conjugate-gradient
 // kernels of the modified-Newton solves.  Vectors are [6][N] doubles.
@@ -173,17 +173,20 @@ __global__ __launch_bounds__(256) void k_im_predict(const uint8_t* __restrict__ 
     q[i] = mode[i] == 0 ? qn[i] + dt * vn[i] + 0.5 * dt * dt * an[i] : qn[i] + dt * vp[i];
 }
 
+// generalised-alpha parameters: am = alpha_m, af = alpha_f (HHT: am = 0,
+// af = -alpha)
 struct ImArgs {
     const uint8_t* __restrict__ mode;
     const double* __restrict__ M;      // [6][N] lumped diagonal
     const double *qn, *vn, *an, *gn, *fn, *f1;
-    double dt, alpha, beta, gamma;
+    double dt, am, af, beta, gamma;
     int64_t N;
 };
 
 // a = (q - q_n - dt v_n - dt^2 (1/2 - beta) a_n) / (beta dt^2),
-// rhs = (1 + alpha)(g + f1) - alpha (g_n + f_n), R = rhs - M a on free DoFs;
-// block partials of |R_F|^2, |(M a)_F|^2, |rhs_F|^2
+// rhs = (1 - af)(g + f1) + af (g_n + f_n) - am M a_n,
+// R = rhs - (1 - am) M a on free DoFs;
+// block partials of |R_F|^2, |((1 - am) M a)_F|^2, |rhs_F|^2
 __global__ __launch_bounds__(IM_THREADS) void k_im_residual(ImArgs ia, const double* __restrict__ q,
                                                             const double* __restrict__ g, double* __restrict__ Rv,
                                                             double* __restrict__ part)
@@ -195,8 +198,9 @@ __global__ __launch_bounds__(IM_THREADS) void k_im_residual(ImArgs ia, const dou
     for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
         const double base = ia.qn[i] + ia.dt * ia.vn[i] + ia.dt * ia.dt * (0.5 - ia.beta) * ia.an[i];
         const double a = (q[i] - base) / bdt2;
-        const double rhs = (1.0 + ia.alpha) * (g[i] + ia.f1[i]) - ia.alpha * (ia.gn[i] + ia.fn[i]);
-        const double ma = ia.M[i] * a;
+        const double rhs =
+            (1.0 - ia.af) * (g[i] + ia.f1[i]) + ia.af * (ia.gn[i] + ia.fn[i]) - ia.am * ia.M[i] * ia.an[i];
+        const double ma = (1.0 - ia.am) * ia.M[i] * a;
         double r = 0.0;
         if (ia.mode[i] == 0) {
             r = rhs - ma;
@@ -237,8 +241,9 @@ __global__ __launch_bounds__(256) void k_im_accept(ImArgs ia, const double* __re
         const double base = ia.qn[i] + ia.dt * ia.vn[i] + ia.dt * ia.dt * (0.5 - ia.beta) * ia.an[i];
         const double a = (qq - base) / bdt2;
         const double v = ia.vn[i] + ia.dt * ((1.0 - ia.gamma) * ia.an[i] + ia.gamma * a);
-        const double rhs = (1.0 + ia.alpha) * (g[i] + ia.f1[i]) - ia.alpha * (ia.gn[i] + ia.fn[i]);
-        const double ma = ia.M[i] * a;
+        const double rhs =
+            (1.0 - ia.af) * (g[i] + ia.f1[i]) + ia.af * (ia.gn[i] + ia.fn[i]) - ia.am * ia.M[i] * ia.an[i];
+        const double ma = (1.0 - ia.am) * ia.M[i] * a;
         const double Ft = ia.mode[i] == 0 ? ia.f1[i] : ma - rhs;
         dwe += 0.5 * (fext[i] + Ft) * (qq - ia.qn[i]);
         wk += 0.5 * ia.M[i] * v * v;

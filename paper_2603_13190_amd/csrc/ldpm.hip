@@ -128,7 +128,7 @@ struct ldpm_system {
     void* pt_mem = nullptr;
     // implicit HHT-alpha integrator (device buffers allocated at its first call)
     bool imp_on = false;
-    double imp_dt = 0.0, imp_alpha = 0.0;
+    double imp_dt = 0.0, imp_am = 0.0, imp_af = 0.0;
     void* im_mem = nullptr;
     double *im_q, *im_qn, *im_vn, *im_an, *im_gn, *im_fn, *im_f1, *im_vp, *im_g, *im_R, *im_M, *im_diag, *im_y;
     double *cg_x, *cg_r, *cg_z, *cg_p, *cg_Ap, *cg_sc, *cg_part, *im_red;
@@ -1376,7 +1376,7 @@ ldpm_status ldpm_perturb(ldpm_system* s, const double* delta, double* work)
 }
 
 // ---------------------------------------------------------------------------
-// implicit HHT-alpha integration (modified Newton on the initial elastic
+// implicit generalised-alpha / HHT-alpha integration (modified Newton on the initial elastic
 // stiffness, inner solves by Jacobi-preconditioned conjugate gradients with
 // the stiffness applied matrix-free by the facet kernel of the elastic law)
 // ---------------------------------------------------------------------------
@@ -1552,15 +1552,17 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
     if (s->mblk) return fail(LDPM_ERR_ARG, "the implicit integrator takes the lumped diagonal mass only");
     if (s->sg_on || s->cp_on) return fail(LDPM_ERR_STATE, "surrogate or capture active");
     if (!(o->dt > 0) || !std::isfinite(o->dt)) return fail(LDPM_ERR_ARG, "implicit dt must be positive");
-    if (!(o->alpha >= -1.0 / 3.0 - 1e-15 && o->alpha <= 0.0)) return fail(LDPM_ERR_ARG, "alpha must lie in [-1/3, 0]");
+    if (!(o->alpha_m >= -1.0 && o->alpha_m <= o->alpha_f + 1e-15 && o->alpha_f <= 0.5 + 1e-15))
+        return fail(LDPM_ERR_ARG, "alpha_m <= alpha_f <= 1/2 and alpha_m >= -1 are required");
     if (!(o->tol > 0) || o->max_iter < 1 || !(o->cg_tol > 0) || o->cg_max_iter < 1)
         return fail(LDPM_ERR_ARG, "tolerances and iteration limits must be positive");
     if (!s->imp_on && s->step > 0) return fail(LDPM_ERR_STATE, "explicit steps were taken on this handle");
-    if (s->imp_on && (o->dt != s->imp_dt || o->alpha != s->imp_alpha))
-        return fail(LDPM_ERR_ARG, "dt and alpha are fixed after the first implicit step");
+    if (s->imp_on && (o->dt != s->imp_dt || o->alpha_m != s->imp_am || o->alpha_f != s->imp_af))
+        return fail(LDPM_ERR_ARG, "dt, alpha_m and alpha_f are fixed after the first implicit step");
     const int64_t N = s->N, T = s->T, F = s->F;
-    const double dt = o->dt, al = o->alpha, be = (1.0 - al) * (1.0 - al) / 4.0, ga = 0.5 - al;
-    const double cM = 1.0 / (be * dt * dt), cK = 1.0 + al;
+    const double dt = o->dt, am = o->alpha_m, af = o->alpha_f;
+    const double be = (1.0 - am + af) * (1.0 - am + af) / 4.0, ga = 0.5 - am + af;
+    const double cM = (1.0 - am) / (be * dt * dt), cK = 1.0 - af;
     hipError_t e = hipSuccess;
     if (!s->im_mem) {
         e = im_alloc(s);
@@ -1568,7 +1570,7 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
     }
     const int64_t n6 = 6 * N;
     const unsigned b6 = blocks_for(n6, 256);
-    ImArgs ia{s->mode, s->im_M, s->im_qn, s->im_vn, s->im_an, s->im_gn, s->im_fn, s->im_f1, dt, al, be, ga, N};
+    ImArgs ia{s->mode, s->im_M, s->im_qn, s->im_vn, s->im_an, s->im_gn, s->im_fn, s->im_f1, dt, am, af, be, ga, N};
     if (!s->imp_on) {
         // committed state from the node records, lumped masses, K_eff diagonal
         hipLaunchKernelGGL(k_im_unpack, dim3(b6), dim3(256), 0, s->stream, (const double*)s->node, N, s->im_qn, s->im_vn);
@@ -1606,7 +1608,8 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
                            (const double*)s->im_vn, N);
         s->imp_on = true;
         s->imp_dt = dt;
-        s->imp_alpha = al;
+        s->imp_am = am;
+        s->imp_af = af;
     }
     int64_t newton = 0, cgits = 0, notconv = 0;
     double maxres = 0.0;

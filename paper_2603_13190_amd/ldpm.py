@@ -112,8 +112,8 @@ class FieldStats(C.Structure):
 
 
 class ImplicitOpts(C.Structure):
-    _fields_ = [("dt", C.c_double), ("alpha", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32)]
+    _fields_ = [("dt", C.c_double), ("alpha_m", C.c_double), ("alpha_f", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32)]
 
 
 class ImplicitStats(C.Structure):
@@ -507,9 +507,17 @@ class System:
         _check(lib().ldpm_perturb(self.h, _p(d, _dp), C.byref(w)))
         return float(w.value)
 
-    def implicit_step(self, n, dt, alpha=0.0, tol=1e-8, max_iter=100, cg_tol=1e-10, cg_max_iter=5000):
-        """n implicit HHT-alpha steps; returns the iteration statistics."""
-        o = ImplicitOpts(float(dt), float(alpha), float(tol), int(max_iter), float(cg_tol), int(cg_max_iter))
+    def implicit_step(self, n, dt, alpha=0.0, rho_inf=None, tol=1e-8, max_iter=100, cg_tol=1e-10,
+                      cg_max_iter=5000):
+        """n implicit steps: HHT-alpha (alpha in [-1/3, 0]), or the
+        generalised-alpha method when rho_inf is given; returns the iteration
+        statistics."""
+        if rho_inf is None:
+            am, af = 0.0, -float(alpha)
+        else:
+            r = float(rho_inf)
+            am, af = (2.0 * r - 1.0) / (r + 1.0), r / (r + 1.0)
+        o = ImplicitOpts(float(dt), am, af, float(tol), int(max_iter), float(cg_tol), int(cg_max_iter))
         st = ImplicitStats()
         _check(lib().ldpm_implicit_step(self.h, C.byref(o), int(n), C.byref(st)))
         return {f: getattr(st, f) for f, _ in ImplicitStats._fields_}
@@ -624,9 +632,17 @@ class Mlp:
         _check(lib().ldpm_perturb(self.h, _p(d, _dp), C.byref(w)))
         return float(w.value)
 
-    def implicit_step(self, n, dt, alpha=0.0, tol=1e-8, max_iter=100, cg_tol=1e-10, cg_max_iter=5000):
-        """n implicit HHT-alpha steps; returns the iteration statistics."""
-        o = ImplicitOpts(float(dt), float(alpha), float(tol), int(max_iter), float(cg_tol), int(cg_max_iter))
+    def implicit_step(self, n, dt, alpha=0.0, rho_inf=None, tol=1e-8, max_iter=100, cg_tol=1e-10,
+                      cg_max_iter=5000):
+        """n implicit steps: HHT-alpha (alpha in [-1/3, 0]), or the
+        generalised-alpha method when rho_inf is given; returns the iteration
+        statistics."""
+        if rho_inf is None:
+            am, af = 0.0, -float(alpha)
+        else:
+            r = float(rho_inf)
+            am, af = (2.0 * r - 1.0) / (r + 1.0), r / (r + 1.0)
+        o = ImplicitOpts(float(dt), am, af, float(tol), int(max_iter), float(cg_tol), int(cg_max_iter))
         st = ImplicitStats()
         _check(lib().ldpm_implicit_step(self.h, C.byref(o), int(n), C.byref(st)))
         return {f: getattr(st, f) for f, _ in ImplicitStats._fields_}

@@ -97,6 +97,21 @@ def test_inelastic_tension_before_the_peak():
         assert abs(eg[k] - eo[k]) <= 1e-9 * abs(eo[k]), (k, eg[k], eo[k])
 
 
+@pytest.mark.parametrize("rho_inf", [0.8, 0.3])
+def test_generalised_alpha(rho_inf):
+    """Generalised-alpha (a_m = (2 rho - 1)/(rho + 1), a_f = rho/(rho + 1)):
+    elastic tension and inelastic tension up to the peak."""
+    from oracle.implicit import gen_alpha_params
+    am, af = gen_alpha_params(rho_inf)
+    for s, n in ((el_tension(), 60), (inel_tension(), 19)):
+        dt = 10 * s["dt"]
+        o = O.Oracle(s)
+        HHT(o, s, dt=dt, tol=OPTS["tol"], max_iter=OPTS["max_iter"], alpha_m=am, alpha_f=af).step(n)
+        g = gpu(s)
+        g.implicit_step(n, dt, rho_inf=rho_inf, **OPTS)
+        compare(g, o, 1e-9, f"generalised-alpha rho={rho_inf}")
+
+
 def test_implicit_is_deterministic_and_resumes_in_chunks():
     s = inel_tension()
     dt = 10 * s["dt"]
@@ -140,6 +155,6 @@ def test_implicit_error_paths():
     with pytest.raises(LdpmError, match="fixed"):
         g.implicit_step(1, 2 * dt, **OPTS)
     with pytest.raises(LdpmError, match="alpha"):
-        gpu(s).implicit_step(1, dt, alpha=-0.5)
+        gpu(s).implicit_step(1, dt, alpha=-0.6)
     with pytest.raises(LdpmError, match="lumped"):
         gpu(S.mass_variant(s, "cell_block")).implicit_step(1, dt)

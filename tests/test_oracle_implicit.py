@@ -20,7 +20,7 @@ import pytest
 import scipy.linalg as sl
 
 import oracle as O
-from oracle.implicit import HHT, elastic_stiffness
+from oracle.implicit import HHT, elastic_stiffness, gen_alpha_params
 from paper_2603_13190_amd import specimen as S
 from tests.conftest import cached
 
@@ -96,14 +96,18 @@ def test_trapezoidal_modal_phase(which, W):
         assert np.abs(o.q.ravel() - expect).max() < 1e-8 * amp * np.abs(phi[:, which]).max(), (n, W)
 
 
-def _mode_run(which, W, alpha, n):
+def _mode_run(which, W, alpha, n, rho_inf=None):
     s = dict(_few_elastic())
     w2, phi, _ = _modes(s)
     w = math.sqrt(w2[which])
     amp = 1e-3 / np.abs(phi[:, which]).max()
     s["q0"] = (amp * phi[:, which]).reshape(-1, 6)
     o = O.Oracle(s)
-    h = HHT(o, s, dt=W / w, alpha=alpha, tol=1e-12, max_iter=5)
+    if rho_inf is None:
+        h = HHT(o, s, dt=W / w, alpha=alpha, tol=1e-12, max_iter=5)
+    else:
+        am, af = gen_alpha_params(rho_inf)
+        h = HHT(o, s, dt=W / w, tol=1e-12, max_iter=5, alpha_m=am, alpha_f=af)
     peak = 0.0
     for _ in range(n):
         h.step(1)
@@ -125,7 +129,20 @@ def test_hht_damps_high_frequencies_and_keeps_low_ones():
     assert peak > 0.999 and end > 0.99
 
 
-def test_hht_is_second_order():
+def test_generalised_alpha_spectral_radius_controls_high_frequencies():
+    """Generalised-alpha with rho_inf = 0 annihilates the highest mode at
+    W = 1e4 (below 1e-6 in 10 steps); rho_inf = 1 keeps it; a low mode keeps
+    its amplitude for rho_inf = 0.8."""
+    end, _ = _mode_run(-1, 1e4, None, 10, rho_inf=0.0)
+    assert end < 1e-6
+    end, peak = _mode_run(-1, 1e4, None, 40, rho_inf=1.0)
+    assert end > 0.999 and abs(peak - 1.0) < 1e-6
+    _, peak = _mode_run(6, 0.05, None, 126, rho_inf=0.8)
+    assert peak > 0.999
+
+
+@pytest.mark.parametrize("rho_inf", [None, 0.8])
+def test_hht_is_second_order(rho_inf):
     s = dict(_few_elastic())
     w2, phi, _ = _modes(s)
     w = math.sqrt(w2[6])
@@ -133,10 +150,11 @@ def test_hht_is_second_order():
     s["q0"] = (amp * phi[:, 6]).reshape(-1, 6)
     T = 2.75 * (2 * math.pi / w)        # cos(w T) = 0: the error is the phase error
     errs = []
+    am, af = gen_alpha_params(rho_inf) if rho_inf is not None else (0.0, 0.1)
     for k in (1, 2):
         n = 40 * k
         o = O.Oracle(s)
-        HHT(o, s, dt=T / n, alpha=-0.1, tol=1e-12, max_iter=5).step(n)
+        HHT(o, s, dt=T / n, tol=1e-12, max_iter=5, alpha_m=am, alpha_f=af).step(n)
         errs.append(np.abs(o.q.ravel() - amp * phi[:, 6] * math.cos(w * T)).max())
     assert 3.5 < errs[0] / errs[1] < 4.5
 
