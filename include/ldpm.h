@@ -364,8 +364,9 @@ ldpm_status ldpm_volumetric_strain(ldpm_system *s, double *ev);
  * limit.  The reduction order depends on n only (bitwise reproducible).
  * IEEE results for degenerate fields: pearson is NaN when either field is
  * constant, nrmse is inf or NaN when max(ref) is 0.  Runs on `stream`
- * (hipStream_t or NULL), allocates a small temporary device buffer and
- * synchronises the stream.                                                 */
+ * (hipStream_t or NULL) and synchronises it.  The first call on a device
+ * allocates a 128 KiB buffer kept for the process; concurrent calls are
+ * serialised.                                                              */
 typedef struct {
     int64_t n;
     double mean_x, mean_ref;

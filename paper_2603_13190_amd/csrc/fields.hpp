@@ -72,21 +72,67 @@ __device__ __forceinline__ void last_strain(const FacetGeo& g, const double* __r
 
 // Crack opening of every facet: w = len (e - E^{-1} t), E = E0 diag(1, a, a),
 // w_N = max(w_N, 0); out [4][F] = w_N, w_M, w_L, |w|.  first: no law
-// evaluation yet (the history belongs to the undeformed state).
-template <typename R>
-__global__ __launch_bounds__(256) void k_crack(NodeArgs na, FacetArgs<R> fa, double E0, double aE0, double dt,
-                                               int first, double* __restrict__ out)
+// evaluation yet (the history belongs to the undeformed state).  One block
+// per TB tetrahedra: the 4 TB node records (q, v) are staged in LDS once
+// and read by the tets' 12 facets, one lane per facet.
+template <typename R, int TB>
+__global__ __launch_bounds__(12 * TB) void k_crack(NodeArgs na, FacetArgs<R> fa, double E0, double aE0, double dt,
+                                                   int first, double* __restrict__ out)
 {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t F = fa.F;
-    if (f >= F) return;
-    const FacetGeo g = facet_geo(fa, na.tet, na.T, f);
-    double e[3] = {0.0, 0.0, 0.0};
-    if (!first) last_strain(g, na.node, dt, e);
-    const double t0 = (double)fa.ht[f], t1 = (double)fa.ht[F + f], t2 = (double)fa.ht[2 * F + f];
-    double wN = g.len * (e[0] - t0 / E0);
-    const double wM = g.len * (e[1] - t1 / aE0);
-    const double wL = g.len * (e[2] - t2 / aE0);
+    constexpr int NS = 4 * TB;
+    __shared__ double s_u[6][NS];  // q - dt v: the configuration of the last law evaluation
+    const int tid = threadIdx.x;
+    const int64_t T = na.T, F = fa.F;
+    const int64_t tet0 = (int64_t)blockIdx.x * TB;
+    // facet data first (independent of the staging)
+    const int tl = tid / 12;
+    const bool valid = tet0 + tl < T;
+    const int64_t f = (tet0 + tl) * 12 + (tid % 12);
+    int32_t rc = 0;
+    double n[3] = {0, 0, 0}, m[3] = {0, 0, 0}, cI[3] = {0, 0, 0}, t[3] = {0, 0, 0}, len = 1.0;
+    if (valid) {
+        rc = fa.rec[f];
+        const R* fr = fa.frame + (int64_t)(rc & 0x0fffffff) * 8;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            n[c] = (double)fr[c];
+            m[c] = (double)fr[3 + c];
+            cI[c] = (double)fa.cI[c * F + f];
+            t[c] = (double)fa.ht[c * F + f];
+        }
+        len = (double)fr[6];
+    }
+    if (tid < NS) {
+        const int ttl = tid % TB, a = tid / TB;
+        if (tet0 + ttl < T) {
+            const double* r = na.node + (int64_t)na.tet[(int64_t)a * T + tet0 + ttl] * 16;
+#pragma unroll
+            for (int c = 0; c < 6; c++) s_u[c][tid] = first ? 0.0 : r[c] - dt * r[6 + c];
+        }
+    }
+    __syncthreads();
+    if (!valid) return;
+    const int aI = (rc >> 28) & 3, aJ = (rc >> 30) & 3;
+    const int sI = aI * TB + tl, sJ = aJ * TB + tl;
+    const double l[3] = {n[1] * m[2] - n[2] * m[1], n[2] * m[0] - n[0] * m[2], n[0] * m[1] - n[1] * m[0]};
+    const double cJ[3] = {cI[0] - len * n[0], cI[1] - len * n[1], cI[2] - len * n[2]};
+    double uI[6], uJ[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        uI[c] = s_u[c][sI];
+        uJ[c] = s_u[c][sJ];
+    }
+    // [[u]] = u_J + th_J x c^J - u_I - th_I x c^I (eq. strain1)
+    double d[3];
+    d[0] = uJ[0] - uI[0] + (uJ[4] * cJ[2] - uJ[5] * cJ[1]) - (uI[4] * cI[2] - uI[5] * cI[1]);
+    d[1] = uJ[1] - uI[1] + (uJ[5] * cJ[0] - uJ[3] * cJ[2]) - (uI[5] * cI[0] - uI[3] * cI[2]);
+    d[2] = uJ[2] - uI[2] + (uJ[3] * cJ[1] - uJ[4] * cJ[0]) - (uI[3] * cI[1] - uI[4] * cI[0]);
+    const double e0 = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) / len;
+    const double e1 = (m[0] * d[0] + m[1] * d[1] + m[2] * d[2]) / len;
+    const double e2 = (l[0] * d[0] + l[1] * d[1] + l[2] * d[2]) / len;
+    double wN = len * (e0 - t[0] / E0);
+    const double wM = len * (e1 - t[1] / aE0);
+    const double wL = len * (e2 - t[2] / aE0);
     wN = wN > 0.0 ? wN : 0.0;
     out[f] = wN;
     out[F + f] = wM;
@@ -212,8 +258,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_range_sum(const double* __restr
 
 // ---------------------------------------------------------------------------
 // field comparison: count, means, centred second moments and co-moment,
-// sum of squared differences and the maximum of the reference, merged
-// pairwise (Chan et al.'s update of Welford's recurrence) in a fixed tree
+// sum of squared differences and the maximum of the reference; per lane
+// from shifted sums, then merged pairwise (Chan et al.'s combination) in a
+// fixed tree
 // ---------------------------------------------------------------------------
 struct Moments {
     double n, mx, mr, sxx, srr, sxr, sse, rmax;
@@ -255,29 +302,52 @@ __device__ Moments block_merge(Moments m)
 }
 
 // one partial per block; thread i of block b takes elements
-// i + CMP_THREADS b + CMP_THREADS G k, k = 0, 1, ... (coalesced)
+// i + CMP_THREADS b + CMP_THREADS G k, k = 0, 1, ... (coalesced), and sums
+// them shifted by its first pair (no division per element; the shift keeps
+// the centred sums well conditioned), then forms its moments
 __global__ __launch_bounds__(CMP_THREADS) void k_cmp_partial(const double* __restrict__ x,
                                                              const double* __restrict__ r, int64_t n, double cap,
                                                              int use_cap, Moments* __restrict__ part)
 {
-    Moments m{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY};
+    double cnt = 0.0, kx = 0.0, kr = 0.0, sx = 0.0, sr = 0.0, sxx = 0.0, srr = 0.0, sxr = 0.0, sse = 0.0;
+    double rmax = -INFINITY;
     const int64_t stride = (int64_t)gridDim.x * CMP_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * CMP_THREADS + threadIdx.x; i < n; i += stride) {
+    const int64_t i0 = (int64_t)blockIdx.x * CMP_THREADS + threadIdx.x;
+    if (i0 < n) {
+        kx = x[i0];
+        kr = r[i0];
+        if (use_cap) {
+            kx = kx < cap ? kx : cap;
+            kr = kr < cap ? kr : cap;
+        }
+    }
+    for (int64_t i = i0; i < n; i += stride) {
         double a = x[i], b = r[i];
         if (use_cap) {
             a = a < cap ? a : cap;
             b = b < cap ? b : cap;
         }
-        m.n += 1.0;
-        const double inv = 1.0 / m.n;
-        const double da = a - m.mx, db = b - m.mr;
-        m.mx += da * inv;
-        m.mr += db * inv;
-        m.sxx += da * (a - m.mx);
-        m.srr += db * (b - m.mr);
-        m.sxr += da * (b - m.mr);
-        m.sse += (a - b) * (a - b);
-        m.rmax = b > m.rmax ? b : m.rmax;
+        const double da = a - kx, db = b - kr;
+        cnt += 1.0;
+        sx += da;
+        sr += db;
+        sxx += da * da;
+        srr += db * db;
+        sxr += da * db;
+        sse += (a - b) * (a - b);
+        rmax = b > rmax ? b : rmax;
+    }
+    Moments m{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY};
+    if (cnt > 0.0) {
+        const double inv = 1.0 / cnt;
+        m.n = cnt;
+        m.mx = kx + sx * inv;
+        m.mr = kr + sr * inv;
+        m.sxx = sxx - sx * sx * inv;
+        m.srr = srr - sr * sr * inv;
+        m.sxr = sxr - sx * sr * inv;
+        m.sse = sse;
+        m.rmax = rmax;
     }
     m = block_merge(m);
     if (threadIdx.x == 0) part[blockIdx.x] = m;

@@ -37,6 +37,7 @@
 #include <type_traits>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -1261,10 +1262,10 @@ ldpm_status ldpm_crack_opening(ldpm_system* s, double* w)
     // implicit: at the committed q_n itself
     const double dtl = s->imp_on ? 0.0 : s->dt;
     if (s->prec == LDPM_PREC_MIXED)
-        hipLaunchKernelGGL(k_crack<float>, dim3(blocks_for(s->F, 256)), dim3(256), 0, s->stream, na,
+        hipLaunchKernelGGL((k_crack<float, 16>), dim3(blocks_for(s->T, 16)), dim3(192), 0, s->stream, na,
                            facet_args<float>(s), E0, aE0, dtl, first, w);
     else
-        hipLaunchKernelGGL(k_crack<double>, dim3(blocks_for(s->F, 256)), dim3(256), 0, s->stream, na,
+        hipLaunchKernelGGL((k_crack<double, 16>), dim3(blocks_for(s->T, 16)), dim3(192), 0, s->stream, na,
                            facet_args<double>(s), E0, aE0, dtl, first, w);
     HIP_TRY(hipGetLastError());
     return LDPM_OK;
@@ -1293,11 +1294,19 @@ ldpm_status ldpm_compare_fields(const double* x, const double* ref, int64_t n, d
         return fail(LDPM_ERR_ARG, "compare_fields: x and ref must be device memory of the current GPU");
     hipStream_t st = (hipStream_t)stream;
     const int G = (int)std::min<int64_t>(CMP_MAX_BLOCKS, (n + CMP_THREADS - 1) / CMP_THREADS);
-    void* mem = nullptr;
-    const size_t bytes = (size_t)G * sizeof(Moments) + 8 * sizeof(double);
-    if (hipMalloc(&mem, bytes) != hipSuccess) return fail(LDPM_ERR_ALLOC, "compare_fields: hipMalloc(%zu) failed", bytes);
+    // one buffer per device (partials and result), kept for the process;
+    // calls are serialised (each waits for its stream before returning)
+    static std::mutex mtx;
+    static std::unordered_map<int, void*> bufs;
+    std::lock_guard<std::mutex> lock(mtx);
+    void*& mem = bufs[dev];
+    const size_t bytes = (size_t)CMP_MAX_BLOCKS * sizeof(Moments) + 8 * sizeof(double);
+    if (!mem && hipMalloc(&mem, bytes) != hipSuccess) {
+        mem = nullptr;
+        return fail(LDPM_ERR_ALLOC, "compare_fields: hipMalloc(%zu) failed", bytes);
+    }
     Moments* part = (Moments*)mem;
-    double* res = (double*)((char*)mem + (size_t)G * sizeof(Moments));
+    double* res = (double*)((char*)mem + (size_t)CMP_MAX_BLOCKS * sizeof(Moments));
     const int use_cap = (cap > 0.0 && std::isfinite(cap)) ? 1 : 0;
     hipLaunchKernelGGL(k_cmp_partial, dim3(G), dim3(CMP_THREADS), 0, st, x, ref, n, cap, use_cap, part);
     hipLaunchKernelGGL(k_cmp_final, dim3(1), dim3(CMP_THREADS), 0, st, (const Moments*)part, G, res);
@@ -1305,7 +1314,6 @@ ldpm_status ldpm_compare_fields(const double* x, const double* ref, int64_t n, d
     double r[7] = {0, 0, 0, 0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(mem);
     if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "compare_fields failed: %s", hipGetErrorString(e));
     out->n = (int64_t)r[0];
     out->mean_x = r[1];
