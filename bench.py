@@ -447,6 +447,38 @@ def implicit_case(args):
     return rec
 
 
+def tess_case(sysd, reps=3):
+    """Specimen geometry on the device: ldpm_tessellate (host arrays in and
+    out, so transfers and its own allocation are inside the figure) against
+    the input generator's NumPy tessellation and cell integrals, on the same
+    centres, diameters and tetrahedra; the two results are compared."""
+    from paper_2603_13190_amd import ldpm, specimen as S
+    x, d, tets = sysd["x0"], sysd["diam"], np.asarray(sysd["tet_nodes"], np.int64)
+    t = time.perf_counter()
+    fac, tri = S.tessellate(x, d, tets)
+    mass, inertia, vol, roff, cJ = S.cell_mass_properties(x, tets, tri, S.RHO)
+    host_s = time.perf_counter() - t
+    ldpm.tessellate(x, d, tets, S.RHO)              # first call: allocator warm-up
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        g = ldpm.tessellate(x, d, tets, S.RHO)
+        times.append(time.perf_counter() - t)
+    gpu_s = float(np.median(times))
+    ref = dict(fac, mass=mass, inertia=inertia, cell_vol=vol, cell_r=roff, cell_inertia=cJ)
+    diff = 0.0
+    for k in ("facet_cI", "facet_n", "facet_area", "facet_len", "mass", "inertia", "cell_inertia"):
+        a, b = np.asarray(g[k]), np.asarray(ref[k], np.float64)
+        diff = max(diff, float(np.abs(a - b).max() / np.abs(b).max()))
+    same_ids = bool(np.array_equal(g["facet_I"], fac["facet_I"]) and np.array_equal(g["facet_J"], fac["facet_J"]))
+    T = tets.shape[0]
+    log(f"tessellation T={T}: host numpy {host_s:.3f} s, device (incl. transfers) {gpu_s * 1e3:.1f} ms, "
+        f"max rel diff {diff:.2e}, ids equal {same_ids}")
+    return {"n_tets": int(T), "n_facets": int(12 * T), "n_particles": int(x.shape[0]), "host_numpy_s": host_s,
+            "device_s_incl_transfers": gpu_s, "speedup": host_s / gpu_s, "max_rel_diff_vs_host": diff,
+            "facet_ids_equal": same_ids}
+
+
 def cycle_run(sysd, precision, model=None, every=1000, launch=None):
     """Whole cyclic trajectory; nominal stress history, energy error, timing
     (reaction sampling outside the timed spans), surrogate share."""
@@ -634,6 +666,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mass", action="store_true", help="skip the mass-representation case")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-integration case")
+    ap.add_argument("--no-tess", action="store_true", help="skip the device tessellation case")
     ap.add_argument("--mass-steps", type=int, default=60000)
     ap.add_argument("--no-crack", action="store_true",
                     help="skip the crack-pattern comparison and the perturbation study")
@@ -763,6 +796,12 @@ def main():
     elif not args.no_accuracy and "load_prog" in sysd["meta"]:
         gacc64.close()
 
+    # ---- specimen geometry on the device (tessellation + cell integrals) ----
+    if not args.no_tess:
+        r = optional("tessellation", lambda: tess_case(sysd))
+        if r is not None:
+            out["tessellation"] = r
+
     # ---- mass representations: free-vibration spectra, particle kernel ----
     if not args.no_mass:
         r = optional("mass", lambda: mass_case(args))
@@ -809,6 +848,10 @@ def main():
             r = optional(name, fn)
             if r is not None:
                 out[name] = r
+        if not args.no_tess and "cylinder_full" in out and "error" not in out["cylinder_full"]:
+            r = optional("tessellation_cylinder", lambda: tess_case(futs["cylinder"].result()))
+            if r is not None:
+                out["tessellation"] = dict(out.get("tessellation", {}), cylinder_full=r)
         pool.shutdown(cancel_futures=True)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----

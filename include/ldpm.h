@@ -448,6 +448,45 @@ typedef struct {
 ldpm_status ldpm_implicit_step(ldpm_system *s, const ldpm_implicit_opts *opts, int64_t n_steps,
                                ldpm_implicit_stats *stats);
 
+/* ---- On-device tessellation ------------------------------------------------
+ * LDPM geometry from particle centres, diameters and a tetrahedralisation
+ * (the paper's preprocessing: polyhedral cells around the particles and the
+ * triangular facets between them; its own generator is not available, so
+ * this is the construction documented with the project's input generator):
+ * on every tetrahedron edge a point at mid-gap between the particle
+ * surfaces, s = (l + r_a - r_b)/2 from x_a clamped to [0.05, 0.95] l; face
+ * points at the centroids of their edge points; the tetrahedron point at the
+ * centroid of the face points; two facets per edge, (edge point, point of
+ * the face through the edge and the third node c, tetrahedron point),
+ * ordered by edge (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) and then by c.  Facet
+ * k joins I < J (particle ids), n = (x_J - x_I)/l, m = normalise(n x e_k)
+ * with e_k the axis of the smallest |n_k|, A0 the triangle's area, A = A0
+ * n.n0 its projection (eq. balance), c^I from x_I to the triangle centroid.
+ * Cells: the exact cone integrals (centre, facet triangle) give volume,
+ * mass = rho V, the inertia tensor J about the centre and the centroid
+ * offset r.  All arrays are HOST memory owned by the caller; NULL outputs
+ * are skipped.  Runs on `stream` (hipStream_t or NULL), allocates and frees
+ * its device buffers, synchronises.                                        */
+typedef struct {
+    int64_t n_particles, n_tets;
+    const double *x;           /* [3][N] centres */
+    const double *diam;        /* [N] particle diameters (> 0) */
+    const int32_t *tet_nodes;  /* [4][T] four distinct node ids each */
+    double rho;                /* density (> 0) */
+} ldpm_tess_desc;
+typedef struct {
+    int32_t *facet_I, *facet_J;                     /* [F], F = 12 T */
+    double *facet_cI, *facet_n, *facet_m;           /* [3][F] */
+    double *facet_area, *facet_area0, *facet_len;   /* [F] */
+    double *mass, *cell_vol;                        /* [N] */
+    double *rot_inertia, *cell_r;                   /* [3][N]: diagonal of J; centroid offset */
+    double *cell_inertia;                           /* [6][N]: J_xx J_yy J_zz J_xy J_yz J_xz */
+    double *tet_node_cones;                         /* [T][4][10]: each tet's part of its nodes'
+                                                       cells: V, first moment (3), second moment
+                                                       (xx yy zz xy yz xz) about the node */
+} ldpm_tess_out;
+ldpm_status ldpm_tessellate(const ldpm_tess_desc *desc, ldpm_tess_out *out, void *stream);
+
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);
 

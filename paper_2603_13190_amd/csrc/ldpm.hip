@@ -85,6 +85,7 @@ ldpm_status ldpm_fail(ldpm_status st, const char* fmt, ...)
 #include "step_kernels.hpp"
 #include "fields.hpp"
 #include "implicit.hpp"
+#include "tessellate.hpp"
 
 // ---------------------------------------------------------------------------
 // host side
@@ -1665,6 +1666,100 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
         stats->max_residual = maxres;
     }
     return ldpm_sync(s);
+}
+
+// ---------------------------------------------------------------------------
+// on-device tessellation
+// ---------------------------------------------------------------------------
+ldpm_status ldpm_tessellate(const ldpm_tess_desc* d, ldpm_tess_out* o, void* stream)
+{
+    if (!d || !o || !d->x || !d->diam || !d->tet_nodes) return fail(LDPM_ERR_ARG, "null argument");
+    const int64_t N = d->n_particles, T = d->n_tets, F = 12 * T;
+    if (N <= 0 || T <= 0) return fail(LDPM_ERR_ARG, "tessellate: empty input");
+    if (N >= (1ll << 31) || 4 * T >= (1ll << 31)) return fail(LDPM_ERR_ARG, "tessellate: too large for 32-bit ids");
+    if (!(d->rho > 0) || !std::isfinite(d->rho)) return fail(LDPM_ERR_ARG, "tessellate: rho must be positive");
+    if (!finite_all(d->x, 3 * N)) return fail(LDPM_ERR_ARG, "tessellate: non-finite centres");
+    for (int64_t i = 0; i < N; i++)
+        if (!(d->diam[i] > 0) || !std::isfinite(d->diam[i])) return fail(LDPM_ERR_ARG, "tessellate: diameters must be positive");
+    std::vector<int32_t> ptr(N + 1, 0), pos(4 * T);
+    for (int64_t t = 0; t < T; t++)
+        for (int a = 0; a < 4; a++) {
+            const int64_t nd = d->tet_nodes[a * T + t];
+            if (nd < 0 || nd >= N) return fail(LDPM_ERR_ARG, "tessellate: tet %lld: node out of range", (long long)t);
+            for (int b = 0; b < a; b++)
+                if (d->tet_nodes[b * T + t] == nd) return fail(LDPM_ERR_ARG, "tessellate: tet %lld repeats a node", (long long)t);
+            ptr[nd + 1]++;
+        }
+    for (int64_t i = 0; i < N; i++) ptr[i + 1] += ptr[i];
+    {
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t t = 0; t < T; t++)
+            for (int a = 0; a < 4; a++) pos[4 * t + a] = fill[d->tet_nodes[a * T + t]]++;
+    }
+    Carve cv;
+    const size_t o_x = cv.take<double>(3 * N), o_dm = cv.take<double>(N), o_tet = cv.take<int32_t>(4 * T);
+    const size_t o_pos = cv.take<int32_t>(4 * T), o_ptr = cv.take<int32_t>(N + 1);
+    const size_t o_I = cv.take<int32_t>(F), o_J = cv.take<int32_t>(F);
+    const size_t o_cI = cv.take<double>(3 * F), o_n = cv.take<double>(3 * F), o_m = cv.take<double>(3 * F);
+    const size_t o_A = cv.take<double>(F), o_A0 = cv.take<double>(F), o_len = cv.take<double>(F);
+    const size_t o_cone = cv.take<double>(40 * T);
+    const size_t o_mass = cv.take<double>(N), o_vol = cv.take<double>(N), o_r = cv.take<double>(3 * N);
+    const size_t o_Jd = cv.take<double>(3 * N), o_J6 = cv.take<double>(6 * N);
+    const size_t bytes = (cv.off + 255) & ~size_t(255);
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return fail(LDPM_ERR_ALLOC, "tessellate: hipMalloc(%zu) failed", bytes);
+    char* B = (char*)mem;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    auto up = [&](size_t off, const void* src, size_t n) {
+        if (e == hipSuccess) e = hipMemcpyAsync(B + off, src, n, hipMemcpyHostToDevice, st);
+    };
+    up(o_x, d->x, 3 * N * 8);
+    up(o_dm, d->diam, N * 8);
+    up(o_tet, d->tet_nodes, 4 * T * 4);
+    up(o_pos, pos.data(), 4 * T * 4);
+    up(o_ptr, ptr.data(), (N + 1) * 4);
+    TessIn ti{(const double*)(B + o_x), (const double*)(B + o_dm), (const int32_t*)(B + o_tet),
+              (const int32_t*)(B + o_pos), N, T};
+    TessOut to{(int32_t*)(B + o_I), (int32_t*)(B + o_J), (double*)(B + o_cI), (double*)(B + o_n), (double*)(B + o_m),
+               (double*)(B + o_A), (double*)(B + o_A0), (double*)(B + o_len), (double*)(B + o_cone)};
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_tessellate, dim3(blocks_for(T, 128)), dim3(128), 0, st, ti, to);
+        hipLaunchKernelGGL(k_cells, dim3(blocks_for(N, 256)), dim3(256), 0, st, (const int32_t*)(B + o_ptr),
+                           (const double*)(B + o_cone), N, d->rho, (double*)(B + o_mass), (double*)(B + o_vol),
+                           (double*)(B + o_r), (double*)(B + o_Jd), (double*)(B + o_J6));
+        e = hipGetLastError();
+    }
+    auto down = [&](void* dst, size_t off, size_t n) {
+        if (dst && e == hipSuccess) e = hipMemcpyAsync(dst, B + off, n, hipMemcpyDeviceToHost, st);
+    };
+    down(o->facet_I, o_I, F * 4);
+    down(o->facet_J, o_J, F * 4);
+    down(o->facet_cI, o_cI, 3 * F * 8);
+    down(o->facet_n, o_n, 3 * F * 8);
+    down(o->facet_m, o_m, 3 * F * 8);
+    down(o->facet_area, o_A, F * 8);
+    down(o->facet_area0, o_A0, F * 8);
+    down(o->facet_len, o_len, F * 8);
+    down(o->mass, o_mass, N * 8);
+    down(o->cell_vol, o_vol, N * 8);
+    down(o->cell_r, o_r, 3 * N * 8);
+    down(o->rot_inertia, o_Jd, 3 * N * 8);
+    down(o->cell_inertia, o_J6, 6 * N * 8);
+    std::vector<double> cone;
+    if (o->tet_node_cones) {
+        cone.resize((size_t)40 * T);
+        down(cone.data(), o_cone, 40 * T * 8);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "tessellate failed: %s", hipGetErrorString(e));
+    if (o->tet_node_cones)
+        for (int64_t t = 0; t < T; t++)
+            for (int a = 0; a < 4; a++)
+                for (int k = 0; k < 10; k++)
+                    o->tet_node_cones[(t * 4 + a) * 10 + k] = cone[(size_t)pos[4 * t + a] * 10 + k];
+    return LDPM_OK;
 }
 
 ldpm_status ldpm_get_launch(ldpm_system* s, ldpm_launch* o)

@@ -26,7 +26,7 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
            "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_capture_begin",
            "ldpm_capture_end", "ldpm_crack_opening", "ldpm_volumetric_strain", "ldpm_compare_fields",
-           "ldpm_perturb", "ldpm_implicit_step",
+           "ldpm_perturb", "ldpm_implicit_step", "ldpm_tessellate",
            "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
@@ -153,6 +153,7 @@ def lib():
         L.ldpm_get_launch.argtypes = [C.c_void_p, C.POINTER(Launch)]
         L.ldpm_autotune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Launch), _dp,
                                     C.POINTER(TuneTrial), C.c_int32, C.POINTER(C.c_int32)]
+        L.ldpm_tessellate.argtypes = [C.POINTER(TessDesc), C.POINTER(TessOut), C.c_void_p]
         L.ldpm_mlp_num_params.restype = C.c_int32
         L.ldpm_mlp_create.argtypes = [_fp, C.c_void_p, C.POINTER(C.c_void_p)]
         L.ldpm_mlp_set_data.argtypes = [C.c_void_p, _fp, _fp, C.c_int64]
@@ -558,6 +559,64 @@ def compare_fields(x, ref, cap=None, stream=None):
     return {f: getattr(o, f) for f, _ in FieldStats._fields_}
 
 
+class TessDesc(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("n_tets", C.c_int64), ("x", _dp), ("diam", _dp),
+                ("tet_nodes", _ip), ("rho", C.c_double)]
+
+
+class TessOut(C.Structure):
+    _fields_ = [("facet_I", _ip), ("facet_J", _ip), ("facet_cI", _dp), ("facet_n", _dp), ("facet_m", _dp),
+                ("facet_area", _dp), ("facet_area0", _dp), ("facet_len", _dp), ("mass", _dp),
+                ("cell_vol", _dp), ("rot_inertia", _dp), ("cell_r", _dp), ("cell_inertia", _dp),
+                ("tet_node_cones", _dp)]
+
+
+def tessellate(x, diam, tets, rho, cones=False, stream=None):
+    """LDPM facets and cell mass properties from centres x (N, 3), diameters
+    (N,), tetrahedra (T, 4) and density rho, computed on the GPU
+    (ldpm_tessellate).  Returns the generator layout: facet arrays (F,) /
+    (F, 3) in tet-major order, mass (N,), inertia (N, 3) (diagonal of J),
+    cell_inertia (N, 3, 3), cell_vol (N,), cell_r (N, 3); with cones=True
+    also tet_node_cones (T, 4, 10)."""
+    import torch  # noqa: F401  (HIP runtime and stream provider)
+    x = np.asarray(x, dtype=np.float64)
+    tets = np.asarray(tets)
+    N, T = x.shape[0], tets.shape[0]
+    if x.ndim != 2 or x.shape[1] != 3 or tets.ndim != 2 or tets.shape[1] != 4:
+        raise ValueError("x must be (N, 3) and tets (T, 4)")
+    if tets.size and (tets.min() < 0 or tets.max() >= N):
+        raise ValueError("tetrahedron node out of range")
+    F = 12 * T
+    xs = _soa(x)
+    dm = np.ascontiguousarray(diam, dtype=np.float64)
+    if dm.shape != (N,):
+        raise ValueError("diam must be (N,)")
+    tn = _soa(tets, np.int32)
+    d = TessDesc(N, T, _p(xs, _dp), _p(dm, _dp), _p(tn, _ip), float(rho))
+    out = dict(facet_I=np.empty(F, np.int32), facet_J=np.empty(F, np.int32), facet_cI=np.empty((3, F)),
+               facet_n=np.empty((3, F)), facet_m=np.empty((3, F)), facet_area=np.empty(F),
+               facet_area0=np.empty(F), facet_len=np.empty(F), mass=np.empty(N), cell_vol=np.empty(N),
+               rot_inertia=np.empty((3, N)), cell_r=np.empty((3, N)), cell_inertia=np.empty((6, N)))
+    cone = np.empty((T, 4, 10)) if cones else None
+    o = TessOut(*[_p(out[k], _ip if k in ("facet_I", "facet_J") else _dp) for k, _ in TessOut._fields_[:-1]],
+                _p(cone, _dp) if cones else None)
+    st = C.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib().ldpm_tessellate(C.byref(d), C.byref(o), st))
+    J6 = out.pop("cell_inertia")
+    Jf = np.empty((N, 3, 3))
+    for p, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2))):
+        Jf[:, i, j] = J6[p]
+        Jf[:, j, i] = J6[p]
+    res = dict(facet_I=out["facet_I"].astype(np.int64), facet_J=out["facet_J"].astype(np.int64),
+               facet_cI=out["facet_cI"].T.copy(), facet_n=out["facet_n"].T.copy(), facet_m=out["facet_m"].T.copy(),
+               facet_area=out["facet_area"], facet_area0=out["facet_area0"], facet_len=out["facet_len"],
+               mass=out["mass"], inertia=out["rot_inertia"].T.copy(), cell_inertia=Jf, cell_vol=out["cell_vol"],
+               cell_r=out["cell_r"].T.copy())
+    if cones:
+        res["tet_node_cones"] = cone
+    return res
+
+
 class Mlp:
     """GPU trainer of the facet-law surrogate (ldpm_mlp_* of the C-ABI)."""
 
@@ -601,51 +660,6 @@ class Mlp:
         p = np.zeros(self.n_params, dtype=np.float32)
         _check(lib().ldpm_mlp_get_params(self.h, p.ctypes.data_as(_fp)))
         return p
-
-    def crack_opening(self, out=None):
-        """Crack-opening vectors after the last step: device tensor (4, F)
-        = w_N, w_M, w_L, |w| (enqueued on the handle's stream)."""
-        import torch
-        if out is None:
-            out = torch.empty((4, self.F), dtype=torch.float64, device="cuda")
-        _check_out(out, (4, self.F))
-        _check(lib().ldpm_crack_opening(self.h, C.c_void_p(out.data_ptr())))
-        return out
-
-    def volumetric_strain(self, out=None):
-        """e_V per tetrahedron at the last evaluated configuration: device tensor (T,)."""
-        import torch
-        if out is None:
-            out = torch.empty((self.T,), dtype=torch.float64, device="cuda")
-        _check_out(out, (self.T,))
-        _check(lib().ldpm_volumetric_strain(self.h, C.c_void_p(out.data_ptr())))
-        return out
-
-    def perturb(self, delta):
-        """Add delta (N, 6) (generator layout) to the free DoFs; returns the
-        work of the jump."""
-        d = np.asarray(delta, dtype=np.float64)
-        if d.shape != (self.N, 6):
-            raise ValueError("delta must have shape (N, 6)")
-        d = np.ascontiguousarray(d.T)
-        w = C.c_double()
-        _check(lib().ldpm_perturb(self.h, _p(d, _dp), C.byref(w)))
-        return float(w.value)
-
-    def implicit_step(self, n, dt, alpha=0.0, rho_inf=None, tol=1e-8, max_iter=100, cg_tol=1e-10,
-                      cg_max_iter=5000):
-        """n implicit steps: HHT-alpha (alpha in [-1/3, 0]), or the
-        generalised-alpha method when rho_inf is given; returns the iteration
-        statistics."""
-        if rho_inf is None:
-            am, af = 0.0, -float(alpha)
-        else:
-            r = float(rho_inf)
-            am, af = (2.0 * r - 1.0) / (r + 1.0), r / (r + 1.0)
-        o = ImplicitOpts(float(dt), am, af, float(tol), int(max_iter), float(cg_tol), int(cg_max_iter))
-        st = ImplicitStats()
-        _check(lib().ldpm_implicit_step(self.h, C.byref(o), int(n), C.byref(st)))
-        return {f: getattr(st, f) for f, _ in ImplicitStats._fields_}
 
     def close(self):
         if getattr(self, "h", None):

@@ -624,7 +624,10 @@ def boundary_triangles(tets):
 # --------------------------------------------------------------------------
 # specimen assembly
 # --------------------------------------------------------------------------
-def build_geometry(shape: Shape, d0, da, seed, gap=0.1, rho=RHO, vol_fraction=None):
+def build_geometry(shape: Shape, d0, da, seed, gap=0.1, rho=RHO, vol_fraction=None, device=False):
+    """Seeded particles, Delaunay tetrahedra (host), then the tessellation
+    and cell integrals: NumPy on the host, or ldpm_tessellate on the GPU
+    when device=True (same construction, same layout)."""
     rng = np.random.default_rng(seed)
     xs = surface_nodes(shape, d0, rng)
     ds = np.full(xs.shape[0], d0)
@@ -647,6 +650,15 @@ def build_geometry(shape: Shape, d0, da, seed, gap=0.1, rho=RHO, vol_fraction=No
     # Morton order of tetrahedra by centroid
     cen = x[tets].mean(axis=1)
     tets = tets[np.argsort(_morton_keys(cen), kind="stable")]
+    if device:
+        from . import ldpm
+        g = ldpm.tessellate(x, diam, tets, rho, cones=True)
+        c = g.pop("tet_node_cones")
+        tr = c[..., 4:7].sum(-1)
+        em = np.concatenate([np.repeat(rho * c[..., :1], 3, -1), rho * (tr[..., None] - c[..., 4:7])], -1)
+        sysd = dict(x0=x, diam=diam, is_surface=is_surf, tet_nodes=tets.astype(np.int32), **g)
+        sysd["_elem_mass"] = em
+        return sysd
     fac, tri = tessellate(x, diam, tets)
     mass, inertia, cvol, roff, cJ = cell_mass_properties(x, tets, tri, rho)
     sysd = dict(x0=x, diam=diam, is_surface=is_surf, tet_nodes=tets.astype(np.int32),

@@ -1,0 +1,148 @@
+"""On-device tessellation (ldpm_tessellate) against the oracle's
+tessellation (oracle/tessellation.py): facets and cell mass properties of
+the same seeded particle sets, element by element.
+
+Bar: facet ids bit-exact; every floating-point array within 1e-12 of the
+largest magnitude of its kind (both sides evaluate the same closed forms in
+FP64 in a different order: cone sums run over a different number of terms,
+so the error is a few ulps of the largest entry).  The per-(tet, node) cone
+records are checked against the oracle's cells through their per-node sums
+(mass, diagonal inertia).  Host-side argument checks run without a GPU.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle.tessellation import tessellate as ora_tessellate
+from paper_2603_13190_amd import ldpm
+from paper_2603_13190_amd import specimen as S
+from tests.conftest import cached
+
+FLOAT_KEYS = ("facet_cI", "facet_n", "facet_m", "facet_area", "facet_area0", "facet_len", "mass", "inertia",
+              "cell_inertia", "cell_vol", "cell_r")
+TOL = 1e-12
+
+
+def _compare(g, o):
+    for k in ("facet_I", "facet_J"):
+        assert np.array_equal(g[k], np.asarray(o[k])), k
+    for k in FLOAT_KEYS:
+        a, b = np.asarray(g[k]), np.asarray(o[k], dtype=np.float64)
+        assert a.shape == b.shape, k
+        assert np.abs(a - b).max() <= TOL * np.abs(b).max(), (k, np.abs(a - b).max(), np.abs(b).max())
+
+
+def _points(make):
+    s = make()
+    return s["x0"], s["diam"], s["tet_nodes"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["cube30", "single_tet", "few"])
+def test_small_specimens_match_the_oracle(case):
+    make = {"cube30": lambda: S.tension_cube(edge=30.0, d0=4.0, da=8.0, seed=7),
+            "single_tet": S.single_tet, "few": lambda: S.few_particle(12, seed=3)}[case]
+    x, d, t = cached(("tess_pts", case), lambda: _points(make))
+    g = ldpm.tessellate(x, d, t, S.RHO, cones=True)
+    o = ora_tessellate(x, d, t, S.RHO)
+    _compare(g, o)
+    # cone records: per-node sums give the oracle's mass and diagonal inertia
+    c = g["tet_node_cones"]
+    tr = c[..., 4:7].sum(-1)
+    share = np.concatenate([S.RHO * c[..., :1], S.RHO * (tr[..., None] - c[..., 4:7])], -1)   # (T,4,4)
+    N = x.shape[0]
+    acc = np.zeros((N, 4))
+    np.add.at(acc, np.asarray(t).ravel(), share.reshape(-1, 4))
+    assert np.abs(acc[:, 0] - o["mass"]).max() <= TOL * o["mass"].max()
+    assert np.abs(acc[:, 1:] - o["inertia"]).max() <= TOL * o["inertia"].max()
+
+
+@pytest.mark.gpu
+def test_ragged_tet_counts_match_the_oracle():
+    """Tet counts around the 128-lane block edge: the first T tetrahedra of
+    a specimen (nodes renumbered to those used)."""
+    x, d, t = cached(("tess_pts", "cube30"), lambda: _points(lambda: S.tension_cube(edge=30.0, d0=4.0, da=8.0,
+                                                                                       seed=7)))
+    for T in (1, 127, 128, 129, 300):
+        tt = np.asarray(t[:T])
+        used = np.unique(tt)
+        remap = -np.ones(x.shape[0], np.int64)
+        remap[used] = np.arange(used.size)
+        xs, ds, ts = x[used], d[used], remap[tt]
+        _compare(ldpm.tessellate(xs, ds, ts, S.RHO), ora_tessellate(xs, ds, ts, S.RHO))
+
+
+@pytest.mark.gpu
+def test_full_size_tension_cube_matches_the_oracle():
+    """The 100 mm tension cube of the headline benchmark (every facet and
+    cell compared)."""
+    from tests.gpu_util import tension_full
+    s = tension_full()
+    x, d, t = s["x0"], s["diam"], s["tet_nodes"]
+    g = ldpm.tessellate(x, d, t, S.RHO)
+    o = ora_tessellate(x, d, t, S.RHO)
+    _compare(g, o)
+
+
+@pytest.mark.gpu
+def test_tessellated_geometry_runs_the_same_step():
+    """A system assembled from the GPU tessellation steps bit-identically
+    to the one from the input generator's geometry when the two agree to
+    the last bit, else within the FP64 tolerance of the step."""
+    from tests.gpu_util import tension_small
+    s = tension_small()
+    g = ldpm.tessellate(s["x0"], s["diam"], s["tet_nodes"], S.RHO)
+    s2 = dict(s)
+    for k in ("facet_I", "facet_J", "facet_cI", "facet_n", "facet_m", "facet_area", "facet_len", "mass", "inertia"):
+        s2[k] = g[k]
+    a, b = ldpm.System(s), ldpm.System(s2)
+    a.step(50)
+    b.step(50)
+    qa, qb = a.read_state()["q"], b.read_state()["q"]
+    assert np.abs(qa - qb).max() <= 1e-9 * max(np.abs(qa).max(), 1e-30)
+
+
+def _raw(x, d, tets, rho):
+    """Call the C-ABI directly (skipping the binding's own checks)."""
+    L = ldpm.lib()
+    x = np.ascontiguousarray(np.asarray(x, np.float64).T)
+    d = np.ascontiguousarray(d, np.float64)
+    t = np.ascontiguousarray(np.asarray(tets, np.int32).T)
+    desc = ldpm.TessDesc(x.shape[1], t.shape[1], x.ctypes.data_as(ldpm._dp), d.ctypes.data_as(ldpm._dp),
+                         t.ctypes.data_as(ldpm._ip), float(rho))
+    out = ldpm.TessOut()
+    rc = L.ldpm_tessellate(C.byref(desc), C.byref(out), None)
+    return rc, L.ldpm_last_error().decode()
+
+
+X4 = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+
+
+@pytest.mark.parametrize("mod,msg", [
+    (lambda a: dict(a, tets=np.array([[0, 1, 2, 4]])), "out of range"),
+    (lambda a: dict(a, tets=np.array([[0, 1, 2, 2]])), "repeats"),
+    (lambda a: dict(a, d=np.array([0.5, 0.5, 0.0, 0.5])), "diameters"),
+    (lambda a: dict(a, d=np.array([0.5, np.nan, 0.5, 0.5])), "diameters"),
+    (lambda a: dict(a, x=np.where(np.eye(4, 3) > 0, np.inf, X4)), "non-finite"),
+    (lambda a: dict(a, rho=-1.0), "rho"),
+    (lambda a: dict(a, tets=np.zeros((0, 4), np.int32)), "empty"),
+])
+def test_invalid_inputs_are_rejected_on_the_host(mod, msg):
+    a = mod(dict(x=X4, d=np.full(4, 0.5), tets=np.array([[0, 1, 2, 3]]), rho=2.4e-9))
+    rc, err = _raw(a["x"], a["d"], a["tets"], a["rho"])
+    assert rc == ldpm.LDPM_ERR_ARG and msg in err, err
+
+
+@pytest.mark.gpu
+def test_geometry_builder_on_the_device_matches_the_host_builder():
+    """build_geometry(device=True): same particles and tetrahedra, the
+    tessellation, cell integrals and per-tet mass shares from the GPU."""
+    shape = S.Shape("box", (30.0, 30.0, 30.0))
+    h = S.build_geometry(shape, 4.0, 8.0, seed=11)
+    g = S.build_geometry(shape, 4.0, 8.0, seed=11, device=True)
+    for k in ("x0", "diam", "tet_nodes", "facet_I", "facet_J"):
+        assert np.array_equal(np.asarray(g[k]), np.asarray(h[k])), k
+    for k in FLOAT_KEYS + ("_elem_mass",):
+        a, b = np.asarray(g[k]), np.asarray(h[k], np.float64)
+        assert np.abs(a - b).max() <= TOL * np.abs(b).max(), k
