@@ -450,19 +450,21 @@ def implicit_case(args):
 def tess_case(sysd, reps=3):
     """Specimen geometry on the device: ldpm_tessellate (host arrays in and
     out, so transfers and its own allocation are inside the figure) against
-    the input generator's NumPy tessellation and cell integrals, on the same
-    centres, diameters and tetrahedra; the two results are compared."""
+    the input generator's NumPy tessellation, cell integrals and per-tet mass
+    shares, on the same centres, diameters and tetrahedra; the two results
+    are compared."""
     from paper_2603_13190_amd import ldpm, specimen as S
     x, d, tets = sysd["x0"], sysd["diam"], np.asarray(sysd["tet_nodes"], np.int64)
     t = time.perf_counter()
     fac, tri = S.tessellate(x, d, tets)
     mass, inertia, vol, roff, cJ = S.cell_mass_properties(x, tets, tri, S.RHO)
+    S.element_mass_share(x, tets, tri, S.RHO)
     host_s = time.perf_counter() - t
-    ldpm.tessellate(x, d, tets, S.RHO)              # first call: allocator warm-up
+    ldpm.tessellate(x, d, tets, S.RHO, cones=True)  # first call: allocator warm-up
     times = []
     for _ in range(reps):
         t = time.perf_counter()
-        g = ldpm.tessellate(x, d, tets, S.RHO)
+        g = ldpm.tessellate(x, d, tets, S.RHO, cones=True)
         times.append(time.perf_counter() - t)
     gpu_s = float(np.median(times))
     ref = dict(fac, mass=mass, inertia=inertia, cell_vol=vol, cell_r=roff, cell_inertia=cJ)

@@ -1681,7 +1681,7 @@ ldpm_status ldpm_tessellate(const ldpm_tess_desc* d, ldpm_tess_out* o, void* str
     if (!finite_all(d->x, 3 * N)) return fail(LDPM_ERR_ARG, "tessellate: non-finite centres");
     for (int64_t i = 0; i < N; i++)
         if (!(d->diam[i] > 0) || !std::isfinite(d->diam[i])) return fail(LDPM_ERR_ARG, "tessellate: diameters must be positive");
-    std::vector<int32_t> ptr(N + 1, 0), pos(4 * T);
+    std::vector<int32_t> ptr(N + 1, 0), inc(4 * T);
     for (int64_t t = 0; t < T; t++)
         for (int a = 0; a < 4; a++) {
             const int64_t nd = d->tet_nodes[a * T + t];
@@ -1694,11 +1694,11 @@ ldpm_status ldpm_tessellate(const ldpm_tess_desc* d, ldpm_tess_out* o, void* str
     {
         std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
         for (int64_t t = 0; t < T; t++)
-            for (int a = 0; a < 4; a++) pos[4 * t + a] = fill[d->tet_nodes[a * T + t]]++;
+            for (int a = 0; a < 4; a++) inc[fill[d->tet_nodes[a * T + t]]++] = (int32_t)(4 * t + a);
     }
     Carve cv;
     const size_t o_x = cv.take<double>(3 * N), o_dm = cv.take<double>(N), o_tet = cv.take<int32_t>(4 * T);
-    const size_t o_pos = cv.take<int32_t>(4 * T), o_ptr = cv.take<int32_t>(N + 1);
+    const size_t o_inc = cv.take<int32_t>(4 * T), o_ptr = cv.take<int32_t>(N + 1);
     const size_t o_I = cv.take<int32_t>(F), o_J = cv.take<int32_t>(F);
     const size_t o_cI = cv.take<double>(3 * F), o_n = cv.take<double>(3 * F), o_m = cv.take<double>(3 * F);
     const size_t o_A = cv.take<double>(F), o_A0 = cv.take<double>(F), o_len = cv.take<double>(F);
@@ -1717,17 +1717,17 @@ ldpm_status ldpm_tessellate(const ldpm_tess_desc* d, ldpm_tess_out* o, void* str
     up(o_x, d->x, 3 * N * 8);
     up(o_dm, d->diam, N * 8);
     up(o_tet, d->tet_nodes, 4 * T * 4);
-    up(o_pos, pos.data(), 4 * T * 4);
+    up(o_inc, inc.data(), 4 * T * 4);
     up(o_ptr, ptr.data(), (N + 1) * 4);
-    TessIn ti{(const double*)(B + o_x), (const double*)(B + o_dm), (const int32_t*)(B + o_tet),
-              (const int32_t*)(B + o_pos), N, T};
+    TessIn ti{(const double*)(B + o_x), (const double*)(B + o_dm), (const int32_t*)(B + o_tet), N, T};
     TessOut to{(int32_t*)(B + o_I), (int32_t*)(B + o_J), (double*)(B + o_cI), (double*)(B + o_n), (double*)(B + o_m),
                (double*)(B + o_A), (double*)(B + o_A0), (double*)(B + o_len), (double*)(B + o_cone)};
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_tessellate, dim3(blocks_for(T, 128)), dim3(128), 0, st, ti, to);
-        hipLaunchKernelGGL(k_cells, dim3(blocks_for(N, 256)), dim3(256), 0, st, (const int32_t*)(B + o_ptr),
-                           (const double*)(B + o_cone), N, d->rho, (double*)(B + o_mass), (double*)(B + o_vol),
-                           (double*)(B + o_r), (double*)(B + o_Jd), (double*)(B + o_J6));
+        hipLaunchKernelGGL(k_tessellate, dim3(blocks_for(T, kTessTets)), dim3(256), 0, st, ti, to);
+        hipLaunchKernelGGL(k_cells, dim3(blocks_for(N * kCellGroup, 256)), dim3(256), 0, st,
+                           (const int32_t*)(B + o_ptr), (const int32_t*)(B + o_inc), (const double*)(B + o_cone), N,
+                           d->rho, (double*)(B + o_mass), (double*)(B + o_vol), (double*)(B + o_r),
+                           (double*)(B + o_Jd), (double*)(B + o_J6));
         e = hipGetLastError();
     }
     auto down = [&](void* dst, size_t off, size_t n) {
@@ -1746,19 +1746,10 @@ ldpm_status ldpm_tessellate(const ldpm_tess_desc* d, ldpm_tess_out* o, void* str
     down(o->cell_r, o_r, 3 * N * 8);
     down(o->rot_inertia, o_Jd, 3 * N * 8);
     down(o->cell_inertia, o_J6, 6 * N * 8);
-    std::vector<double> cone;
-    if (o->tet_node_cones) {
-        cone.resize((size_t)40 * T);
-        down(cone.data(), o_cone, 40 * T * 8);
-    }
+    down(o->tet_node_cones, o_cone, 40 * T * 8);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(mem);
     if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "tessellate failed: %s", hipGetErrorString(e));
-    if (o->tet_node_cones)
-        for (int64_t t = 0; t < T; t++)
-            for (int a = 0; a < 4; a++)
-                for (int k = 0; k < 10; k++)
-                    o->tet_node_cones[(t * 4 + a) * 10 + k] = cone[(size_t)pos[4 * t + a] * 10 + k];
     return LDPM_OK;
 }
 
