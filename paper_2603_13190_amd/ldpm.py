@@ -483,7 +483,7 @@ class System:
         = w_N, w_M, w_L, |w| (enqueued on the handle's stream)."""
         import torch
         if out is None:
-            out = torch.empty((4, self.F), dtype=torch.float64, device="cuda")
+            out = torch.empty((4, self.F), dtype=torch.float64, device=self.stream.device)
         _check_out(out, (4, self.F))
         _check(lib().ldpm_crack_opening(self.h, C.c_void_p(out.data_ptr())))
         return out
@@ -492,7 +492,7 @@ class System:
         """e_V per tetrahedron at the last evaluated configuration: device tensor (T,)."""
         import torch
         if out is None:
-            out = torch.empty((self.T,), dtype=torch.float64, device="cuda")
+            out = torch.empty((self.T,), dtype=torch.float64, device=self.stream.device)
         _check_out(out, (self.T,))
         _check(lib().ldpm_volumetric_strain(self.h, C.c_void_p(out.data_ptr())))
         return out
@@ -607,7 +607,7 @@ def tessellate(x, diam, tets, rho, cones=False, stream=None):
     for p, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2))):
         Jf[:, i, j] = J6[p]
         Jf[:, j, i] = J6[p]
-    res = dict(facet_I=out["facet_I"].astype(np.int64), facet_J=out["facet_J"].astype(np.int64),
+    res = dict(facet_I=out["facet_I"], facet_J=out["facet_J"],
                facet_cI=out["facet_cI"].T.copy(), facet_n=out["facet_n"].T.copy(), facet_m=out["facet_m"].T.copy(),
                facet_area=out["facet_area"], facet_area0=out["facet_area0"], facet_len=out["facet_len"],
                mass=out["mass"], inertia=out["rot_inertia"].T.copy(), cell_inertia=Jf, cell_vol=out["cell_vol"],

@@ -717,13 +717,13 @@ def _box_faces(x, L, tol):
 
 
 def elastic_vibration_cube(edge=50.0, d0=4.0, da=8.0, seed=1, v0_amp=10.0,
-                           mat=None, dt_fraction=0.8):
+                           mat=None, dt_fraction=0.8, device=False):
     """Elastic cube, all DoFs of the base fixed, initial sinusoidal velocity
     v_x = v0 sin(pi z / 2H), no damping."""
     mat = dict(MATERIAL_MB if mat is None else mat)
     mat["law"] = 0
     shape = Shape("box", (edge, edge, edge))
-    g = build_geometry(shape, d0, da, seed)
+    g = build_geometry(shape, d0, da, seed, device=device)
     x = g["x0"]
     N = x.shape[0]
     faces = _box_faces(x, shape.size, 1e-9)
@@ -742,13 +742,13 @@ def elastic_vibration_cube(edge=50.0, d0=4.0, da=8.0, seed=1, v0_amp=10.0,
 
 
 def tension_cube(edge=100.0, d0=4.0, da=10.0, seed=1, rate=1e-2, ramp=1e-3,
-                 mat=None, dt_fraction=0.8, n_steps=200000):
+                 mat=None, dt_fraction=0.8, n_steps=200000, device=False):
     """Uniaxial tension: bottom face u=0, theta_x=theta_y=0; top face the same
     except u_z following a velocity program ramped over `ramp` seconds to
     rate * height."""
     mat = dict(MATERIAL_MB if mat is None else mat)
     shape = Shape("box", (edge, edge, edge))
-    g = build_geometry(shape, d0, da, seed)
+    g = build_geometry(shape, d0, da, seed, device=device)
     x = g["x0"]
     N = x.shape[0]
     faces = _box_faces(x, shape.size, 1e-9)
@@ -771,13 +771,13 @@ def tension_cube(edge=100.0, d0=4.0, da=10.0, seed=1, rate=1e-2, ramp=1e-3,
 
 def confined_compression_cube(edge=150.0, d0=4.0, da=12.0, seed=1, pressure=20.0,
                               final_strain=2e-2, n_steps=300000, mat=None,
-                              dt_fraction=0.8, ramp_frac=0.1):
+                              dt_fraction=0.8, ramp_frac=0.1, device=False):
     """Lateral pressure as nodal forces (p times a third of each boundary
     triangle's area on the four lateral faces, ramped over the first
     ramp_frac of the run), then a top velocity; bottom u_z = 0."""
     mat = dict(MATERIAL_MB if mat is None else mat)
     shape = Shape("box", (edge, edge, edge))
-    g = build_geometry(shape, d0, da, seed)
+    g = build_geometry(shape, d0, da, seed, device=device)
     x = g["x0"]
     N = x.shape[0]
     L = shape.size
@@ -826,13 +826,13 @@ def confined_compression_cube(edge=150.0, d0=4.0, da=12.0, seed=1, pressure=20.0
 
 
 def sliding_compression_cube(edge, d0=4.0, da=8.0, seed=0, rate=2.5e-2, ramp=1e-3,
-                             mat=None, dt=None, dt_fraction=0.8):
+                             mat=None, dt=None, dt_fraction=0.8, device=False):
     """Unconfined compression between frictionless platens: u_z prescribed on
     top (velocity) and bottom (zero); theta_x, theta_y fixed there; u_x, u_y,
     theta_z free except at the face-centre nodes."""
     mat = dict(MATERIAL_MB if mat is None else mat)
     shape = Shape("box", (edge, edge, edge))
-    g = build_geometry(shape, d0, da, seed)
+    g = build_geometry(shape, d0, da, seed, device=device)
     x = g["x0"]
     N = x.shape[0]
     L = shape.size
@@ -994,7 +994,7 @@ def batch_sliding_compression(n=64, seed=0, edge_range=(50.0, 100.0), d0=4.0, da
 
 
 def cylinder_cycle(D=100.0, H=200.0, d0=2.0, da=4.0, seed=1, eps_t=1.2e-4, eps_c=1.0e-3,
-                   cycles=2, rate=0.2, mat=None, dt_fraction=0.8):
+                   cycles=2, rate=0.2, mat=None, dt_fraction=0.8, device=False):
     """Cylinder (axis z) cycled between tension and compression: bottom face
     u_z = 0, theta_x = theta_y = 0 (centre node pinned laterally); top face
     theta_x = theta_y = 0 and u_z following a triangle wave of nominal strain
@@ -1002,7 +1002,7 @@ def cylinder_cycle(D=100.0, H=200.0, d0=2.0, da=4.0, seed=1, eps_t=1.2e-4, eps_c
     -eps_c H (about half of the compressive peak), `cycles` times."""
     mat = dict(MATERIAL_MB if mat is None else mat)
     shape = Shape("cylinder", (D, H))
-    g = build_geometry(shape, d0, da, seed)
+    g = build_geometry(shape, d0, da, seed, device=device)
     x = g["x0"]
     N = x.shape[0]
     tol = 1e-9

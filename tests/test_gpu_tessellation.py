@@ -146,3 +146,17 @@ def test_geometry_builder_on_the_device_matches_the_host_builder():
     for k in FLOAT_KEYS + ("_elem_mass",):
         a, b = np.asarray(g[k]), np.asarray(h[k], np.float64)
         assert np.abs(a - b).max() <= TOL * np.abs(b).max(), k
+
+
+@pytest.mark.gpu
+def test_specimen_builder_with_device_geometry():
+    """tension_cube(device=True): the same specimen (boundary programs, masks,
+    stable step) as the host-built one, to the tessellation's tolerance."""
+    h = S.tension_cube(edge=30.0, d0=4.0, da=8.0, seed=3)
+    g = S.tension_cube(edge=30.0, d0=4.0, da=8.0, seed=3, device=True)
+    for k in ("dof_mode", "dof_prog", "tet_nodes", "facet_I", "facet_J"):
+        assert np.array_equal(np.asarray(g[k]), np.asarray(h[k])), k
+    assert abs(g["dt"] - h["dt"]) <= 1e-12 * h["dt"]
+    for k in FLOAT_KEYS + ("dof_scale",):
+        a, b = np.asarray(g[k]), np.asarray(h[k], np.float64)
+        assert np.abs(a - b).max() <= TOL * max(np.abs(b).max(), 1e-300), k
