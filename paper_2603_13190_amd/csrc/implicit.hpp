@@ -273,7 +273,8 @@ __global__ __launch_bounds__(256) void k_im_add(const uint8_t* __restrict__ mode
 // ---------------------------------------------------------------------------
 // conjugate gradients on K_eff = cM M + cK K0 over the free DoFs, Jacobi
 // preconditioner; K0 p = -gather(facet kernel of the elastic law at p)
-// scalars: sc[0] = r.z, sc[1] = alpha_cg, sc[2] = beta_cg, sc[3] = r.r
+// scalars: sc[0] = r.z, sc[1] = alpha_cg, sc[2] = beta_cg, sc[3] = r.r,
+// sc[4] = r.r of the right-hand side, sc[8 + parity] = r.z
 // ---------------------------------------------------------------------------
 struct CgArgs {
     const uint8_t* __restrict__ mode;
@@ -312,38 +313,88 @@ __global__ __launch_bounds__(IM_THREADS) void k_cg_init(CgArgs cg, const double*
     }
 }
 
-// Ap = cM M p - cK y (y = -K0 p from the gather) on free DoFs; partial p.Ap
-__global__ __launch_bounds__(IM_THREADS) void k_cg_apply(CgArgs cg, const double* __restrict__ y)
-{
-    double pap = 0.0, u0 = 0.0, u1 = 0.0;
-    const int64_t n6 = 6 * cg.N;
-    const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
-        const double ap = cg.mode[i] == 0 ? cg.cM * cg.M[i] * cg.p[i] - cg.cK * y[i] : 0.0;
-        cg.Ap[i] = ap;
-        pap += cg.p[i] * ap;
-    }
-    block_sum3(pap, u0, u1);
-    if (threadIdx.x == 0) {
-        cg.part[blockIdx.x] = pap;
-        cg.part[gridDim.x + blockIdx.x] = 0.0;
-        cg.part[2 * gridDim.x + blockIdx.x] = 0.0;
-    }
-}
-
-// sc[1] = sc[0] / sum(partials of p.Ap)
-__global__ __launch_bounds__(IM_THREADS) void k_cg_alpha(CgArgs cg, int G)
+// sc[2] = rz_new / sc[0]; sc[0] = rz_new; sc[3] = r.r  (first: only store);
+// used after k_cg_init
+__global__ __launch_bounds__(IM_THREADS) void k_cg_beta(CgArgs cg, int G, int first)
 {
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int i = threadIdx.x; i < G; i += IM_THREADS) a += cg.part[i];
+    for (int i = threadIdx.x; i < G; i += IM_THREADS) {
+        a += cg.part[i];
+        b += cg.part[G + i];
+    }
     block_sum3(a, b, c);
-    if (threadIdx.x == 0) cg.sc[1] = a != 0.0 ? cg.sc[0] / a : 0.0;
+    if (threadIdx.x == 0) {
+        cg.sc[2] = (!first && cg.sc[0] != 0.0) ? a / cg.sc[0] : 0.0;
+        cg.sc[0] = a;
+        cg.sc[3] = b;
+        if (first) {
+            cg.sc[4] = b;  // r.r of the right-hand side
+            cg.sc[8] = a;  // r.z in the parity-0 slot the first update reads
+        }
+    }
 }
 
-// x += alpha p, r -= alpha Ap, z = r / diag; partials r.z, r.r
-__global__ __launch_bounds__(IM_THREADS) void k_cg_update(CgArgs cg)
+// One CG iteration is four kernels: the elastic facet kernel at p, then
+//   k_cg_gather_apply  y = -K0 p per particle, Ap = cM M p - cK y, partials of p.Ap;
+//   k_cg_update        alpha from the p.Ap partials, x += alpha p,
+//                      r -= alpha Ap, z = r / diag, partials of r.z and r.r;
+//   k_cg_newp          beta from the r.z partials, p = z + beta p.
+// Every block reduces the previous kernel's partials itself, in the same
+// fixed order, so all blocks hold the same scalar and no reduction kernel
+// runs in between.  r.z alternates between sc[8] and sc[9] (par = iteration
+// parity), so that the block that stores the new value never overwrites the
+// one the other blocks are still reading.  partA has IM_MAX_BLOCKS slots,
+// partB 2 x IM_MAX_BLOCKS (r.z, then r.r).
+
+// the gather of k_im_gather (PG lanes per particle, same summation order),
+// over particle groups grid-stride, then the operator on the group's 6 DoFs
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_gather_apply(CgArgs cg, const int32_t* __restrict__ ptr,
+                                                         const R* __restrict__ contrib, double* __restrict__ partA)
 {
-    const double al = cg.sc[1];
+    const int64_t N = cg.N;
+    constexpr int GROUPS = 256 / PG;
+    const int lane = (int)(threadIdx.x % PG);
+    double pap = 0.0, u0 = 0.0, u1 = 0.0;
+    for (int64_t I0 = (int64_t)blockIdx.x * GROUPS; I0 < N; I0 += (int64_t)gridDim.x * GROUPS) {
+        const int64_t I = I0 + threadIdx.x / PG;
+        double f[6] = {0, 0, 0, 0, 0, 0};
+        if (I < N) {
+            const int32_t s0 = ptr[I], s1 = ptr[I + 1];
+            for (int32_t q = s0 + lane; q < s1; q += PG) {
+                const R* c = contrib + (int64_t)q * 6;
+#pragma unroll
+                for (int k = 0; k < 6; k++) f[k] += (double)c[k];
+            }
+        }
+#pragma unroll
+        for (int off = PG / 2; off > 0; off >>= 1) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) f[k] += __shfl_xor(f[k], off, PG);
+        }
+        if (I < N && lane < 6) {
+            double y = f[0];
+#pragma unroll
+            for (int k = 1; k < 6; k++) y = (lane == k) ? f[k] : y;
+            const int64_t i = (int64_t)lane * N + I;
+            const double ap = cg.mode[i] == 0 ? cg.cM * cg.M[i] * cg.p[i] - cg.cK * y : 0.0;
+            cg.Ap[i] = ap;
+            pap += cg.p[i] * ap;
+        }
+    }
+    block_sum3(pap, u0, u1);
+    if (threadIdx.x == 0) partA[blockIdx.x] = pap;
+}
+
+// alpha = r.z / p.Ap; x += alpha p, r -= alpha Ap, z = r / diag; partials r.z, r.r
+__global__ __launch_bounds__(IM_THREADS) void k_cg_update(CgArgs cg, const double* __restrict__ partA, int GA,
+                                                          double* __restrict__ partB, int par)
+{
+    double pap = 0.0, u0 = 0.0, u1 = 0.0;
+    for (int i = threadIdx.x; i < GA; i += IM_THREADS) pap += partA[i];
+    block_sum3(pap, u0, u1);
+    const double al = pap != 0.0 ? cg.sc[8 + par] / pap : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cg.sc[1] = al;
     double rz = 0.0, rr = 0.0, u = 0.0;
     const int64_t n6 = 6 * cg.N;
     const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
@@ -359,38 +410,50 @@ __global__ __launch_bounds__(IM_THREADS) void k_cg_update(CgArgs cg)
     }
     block_sum3(rz, rr, u);
     if (threadIdx.x == 0) {
-        cg.part[blockIdx.x] = rz;
-        cg.part[gridDim.x + blockIdx.x] = rr;
-        cg.part[2 * gridDim.x + blockIdx.x] = 0.0;
+        partB[blockIdx.x] = rz;
+        partB[IM_MAX_BLOCKS + blockIdx.x] = rr;
     }
 }
 
-// sc[2] = rz_new / sc[0]; sc[0] = rz_new; sc[3] = r.r  (first: only store)
-__global__ __launch_bounds__(IM_THREADS) void k_cg_beta(CgArgs cg, int G, int first)
+// sc[3] = r.r from the update's partials (one block; the host's stopping test)
+__global__ __launch_bounds__(IM_THREADS) void k_cg_rr(CgArgs cg, const double* __restrict__ partB, int G)
 {
     double a = 0.0, b = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < G; i += IM_THREADS) {
-        a += cg.part[i];
-        b += cg.part[G + i];
+        a += partB[i];
+        b += partB[IM_MAX_BLOCKS + i];
     }
     block_sum3(a, b, c);
-    if (threadIdx.x == 0) {
-        cg.sc[2] = (!first && cg.sc[0] != 0.0) ? a / cg.sc[0] : 0.0;
-        cg.sc[0] = a;
-        cg.sc[3] = b;
-        if (first) cg.sc[4] = b;  // r.r of the right-hand side
-    }
+    if (threadIdx.x == 0) cg.sc[3] = b;
 }
 
-// p = z + beta p (free DoFs), written also to the q slots of node_p
-__global__ __launch_bounds__(256) void k_cg_newp(CgArgs cg, double* __restrict__ node_p)
+// beta = r.z_new / r.z_old; p = z + beta p (free DoFs), written also to the
+// q slots of node_p; block 0 stores r.z_new in the other parity slot
+__global__ __launch_bounds__(IM_THREADS) void k_cg_newp(CgArgs cg, const double* __restrict__ partB, int G,
+                                                        double* __restrict__ node_p, int par)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 6 * cg.N) return;
-    const double p = cg.mode[i] == 0 ? cg.z[i] + cg.sc[2] * cg.p[i] : 0.0;
-    cg.p[i] = p;
-    const int64_t c = i / cg.N, pI = i - c * cg.N;
-    node_p[pI * 16 + c] = p;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < G; i += IM_THREADS) {
+        a += partB[i];
+        b += partB[IM_MAX_BLOCKS + i];
+    }
+    block_sum3(a, b, c);
+    const double rz_old = cg.sc[8 + par];
+    const double be = rz_old != 0.0 ? a / rz_old : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cg.sc[8 + (par ^ 1)] = a;
+        cg.sc[0] = a;
+        cg.sc[2] = be;
+        cg.sc[3] = b;
+    }
+    const int64_t n6 = 6 * cg.N;
+    const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
+    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
+        const double p = cg.mode[i] == 0 ? cg.z[i] + be * cg.p[i] : 0.0;
+        cg.p[i] = p;
+        const int64_t cc = i / cg.N, pI = i - cc * cg.N;
+        node_p[pI * 16 + cc] = p;
+    }
 }
 
 // q_n, v_n from the node records

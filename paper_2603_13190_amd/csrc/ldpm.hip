@@ -132,7 +132,7 @@ struct ldpm_system {
     bool imp_on = false;
     double imp_dt = 0.0, imp_am = 0.0, imp_af = 0.0;
     void* im_mem = nullptr;
-    double *im_q, *im_qn, *im_vn, *im_an, *im_gn, *im_fn, *im_f1, *im_vp, *im_g, *im_R, *im_M, *im_diag, *im_y;
+    double *im_q, *im_qn, *im_vn, *im_an, *im_gn, *im_fn, *im_f1, *im_vp, *im_g, *im_R, *im_M, *im_diag;
     double *cg_x, *cg_r, *cg_z, *cg_p, *cg_Ap, *cg_sc, *cg_part, *im_red;
     double *im_node_p, *im_ht_scr, *im_wint_scr, *im_con_scr, *im_ht_c, *im_hem_c, *im_wint_c;
 };
@@ -1419,15 +1419,14 @@ void launch_facet_plain_l(ldpm_system* s, const NodeArgs& na, const FacetArgs<do
 hipError_t im_alloc(ldpm_system* s)
 {
     const int64_t N = s->N, T = s->T, F = s->F;
-    const int G = (int)im_blocks(6 * N);
     Carve cv;
     const size_t n6 = 6 * N;
     size_t o[32];
     int k = 0;
-    for (int i = 0; i < 13; i++) o[k++] = cv.take<double>(n6);     // im_* vectors
+    for (int i = 0; i < 12; i++) o[k++] = cv.take<double>(n6);     // im_* vectors
     for (int i = 0; i < 5; i++) o[k++] = cv.take<double>(n6);      // cg x r z p Ap
-    o[k++] = cv.take<double>(8);                                    // cg_sc
-    o[k++] = cv.take<double>(3 * (size_t)G);                        // cg_part
+    o[k++] = cv.take<double>(16);                                   // cg_sc
+    o[k++] = cv.take<double>(3 * (size_t)IM_MAX_BLOCKS);            // cg_part (partials)
     o[k++] = cv.take<double>(8);                                    // im_red
     o[k++] = cv.take<double>(16 * N);                               // node_p
     o[k++] = cv.take<double>(3 * F);                                // ht scratch
@@ -1442,10 +1441,10 @@ hipError_t im_alloc(ldpm_system* s)
     if (e != hipSuccess) return e;
     s->im_mem = mem;
     char* B = (char*)mem;
-    double** vec[13] = {&s->im_q, &s->im_qn, &s->im_vn, &s->im_an, &s->im_gn, &s->im_fn, &s->im_f1,
-                        &s->im_vp, &s->im_g, &s->im_R, &s->im_M, &s->im_diag, &s->im_y};
+    double** vec[12] = {&s->im_q, &s->im_qn, &s->im_vn, &s->im_an, &s->im_gn, &s->im_fn, &s->im_f1,
+                        &s->im_vp, &s->im_g, &s->im_R, &s->im_M, &s->im_diag};
     k = 0;
-    for (int i = 0; i < 13; i++) *vec[i] = (double*)(B + o[k++]);
+    for (int i = 0; i < 12; i++) *vec[i] = (double*)(B + o[k++]);
     double** cgv[5] = {&s->cg_x, &s->cg_r, &s->cg_z, &s->cg_p, &s->cg_Ap};
     for (int i = 0; i < 5; i++) *cgv[i] = (double*)(B + o[k++]);
     s->cg_sc = (double*)(B + o[k++]);
@@ -1486,8 +1485,9 @@ hipError_t im_trial(ldpm_system* s, const double* q, int first)
     return hipGetLastError();
 }
 
-// y = -K0 p for the p in the q slots of node_p (elastic law on scratch history)
-void im_k0_apply(ldpm_system* s)
+// tet-node records of -K0 p for the p in the q slots of node_p (elastic law
+// on scratch history); k_cg_gather_apply sums them per particle
+void im_k0_facets(ldpm_system* s)
 {
     NodeArgs na{s->tet, s->im_node_p, s->N, s->T};
     FacetArgs<double> fa = facet_args<double>(s);
@@ -1495,8 +1495,6 @@ void im_k0_apply(ldpm_system* s)
     fa.hemax = nullptr;
     const ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, 0};
     launch_facet_plain_l<0>(s, na, fa, s->im_con_scr, s->im_wint_scr, pr, 1, 1.0);
-    hipLaunchKernelGGL(k_im_gather<double>, dim3(blocks_for(s->N * PG, 256)), dim3(256), 0, s->stream,
-                       (const int32_t*)s->ptr, (const double*)s->im_con_scr, s->N, s->im_y);
 }
 
 // x = K_eff^{-1} R on the free DoFs; returns the iterations
@@ -1513,22 +1511,29 @@ hipError_t im_cg(ldpm_system* s, double cM, double cK, double tol, int max_it, i
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return e;
     const double rr0 = sc[4];
-    int it = 0;
+    // partials: p.Ap of the gather-apply grid, then r.z and r.r of the update grid
+    const int GA = (int)std::min<int64_t>(IM_MAX_BLOCKS, blocks_for(N * PG, 256));
+    double* partA = s->cg_part;
+    double* partB = s->cg_part + IM_MAX_BLOCKS;
+    int it = 0, par = 0;
     if (rr0 > 0.0) {
         while (it < max_it) {
-            im_k0_apply(s);
-            hipLaunchKernelGGL(k_cg_apply, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)s->im_y);
-            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, G);
-            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(IM_THREADS), 0, s->stream, cg);
-            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, G, 0);
+            im_k0_facets(s);
+            hipLaunchKernelGGL(k_cg_gather_apply<double>, dim3(GA), dim3(256), 0, s->stream, cg,
+                               (const int32_t*)s->ptr, (const double*)s->im_con_scr, partA);
+            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partA, GA,
+                               partB, par);
             it++;
             if (it % 8 == 0 || it == max_it) {
+                hipLaunchKernelGGL(k_cg_rr, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partB, G);
                 e = hipMemcpyAsync(sc, s->cg_sc, 64, hipMemcpyDeviceToHost, s->stream);
                 if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
                 if (e != hipSuccess) return e;
                 if (!(sc[3] > tol * tol * rr0)) break;
             }
-            hipLaunchKernelGGL(k_cg_newp, dim3(blocks_for(6 * N, 256)), dim3(256), 0, s->stream, cg, s->im_node_p);
+            hipLaunchKernelGGL(k_cg_newp, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partB, G,
+                               s->im_node_p, par);
+            par ^= 1;
         }
     }
     *its = it;
