@@ -418,8 +418,9 @@ ldpm_status ldpm_perturb(ldpm_system *s, const double *delta, double *work);
  * reactions of prescribed DoFs, which move by dt v_P(t_n + dt/2).  Each step
  * is solved by modified Newton on the free DoFs with the initial elastic
  * stiffness K0: K_eff = (1 - a_m) M / (beta dt^2) + (1 - a_f) K0, its systems
- * solved by Jacobi-preconditioned conjugate gradients with K0 applied
- * matrix-free (the facet kernel of the elastic law).  Every Newton iteration
+ * solved by conjugate gradients with K0 applied matrix-free (the facet
+ * kernel of the elastic law), preconditioned by the inverse 6 x 6 blocks of
+ * K_eff that couple each particle's DoFs with themselves.  Every Newton iteration
  * evaluates the facet law at the trial configuration from the committed
  * history; the last trial is committed when the step is accepted: when
  * |R_F|_2 <= tol (|((1 - a_m) M a)_F|_2 + |rhs_F|_2) or after max_iter

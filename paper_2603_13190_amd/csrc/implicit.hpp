@@ -1,6 +1,6 @@
 // Device side of the implicit generalised-alpha / HHT-alpha integrator: per-DoF vector kernels,
 // the deterministic gather of tet-node records into particle vectors, the
-// diagonal of the initial elastic stiffness, and the conjugate-gradient
+// particle blocks of the initial elastic stiffness, and the conjugate-gradient
 // kernels of the modified-Newton solves.  Vectors are [6][N] doubles.
 // Included once, by ldpm.hip, after step_kernels.hpp.
 #pragma once
@@ -48,9 +48,10 @@ __global__ __launch_bounds__(IM_THREADS) void k_im_reduce3(const double* __restr
     }
 }
 
-// out[k][I] = sum of the tet-node records of particle I (CSR order, PG lanes
-// per particle, the same summation structure as the step's gather)
-template <typename R>
+// out[k][I] = sum of the NV-value tet-node records of particle I (CSR
+// order, PG lanes per particle, the same summation structure as the step's
+// gather)
+template <typename R, int NV = 6>
 __global__ __launch_bounds__(256) void k_im_gather(const int32_t* __restrict__ ptr, const R* __restrict__ contrib,
                                                    int64_t N, double* __restrict__ out)
 {
@@ -58,40 +59,43 @@ __global__ __launch_bounds__(256) void k_im_gather(const int32_t* __restrict__ p
     const int64_t I = gt / PG;
     const int lane = (int)(gt % PG);
     if (I >= N) return;
-    double f[6] = {0, 0, 0, 0, 0, 0};
+    double f[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) f[k] = 0.0;
     const int32_t s0 = ptr[I], s1 = ptr[I + 1];
     for (int32_t s = s0 + lane; s < s1; s += PG) {
-        const R* c = contrib + (int64_t)s * 6;
+        const R* c = contrib + (int64_t)s * NV;
 #pragma unroll
-        for (int k = 0; k < 6; k++) f[k] += (double)c[k];
+        for (int k = 0; k < NV; k++) f[k] += (double)c[k];
     }
 #pragma unroll
     for (int off = PG / 2; off > 0; off >>= 1) {
 #pragma unroll
-        for (int k = 0; k < 6; k++) f[k] += __shfl_xor(f[k], off, PG);
+        for (int k = 0; k < NV; k++) f[k] += __shfl_xor(f[k], off, PG);
     }
-    if (lane < 6) {
-        double v = f[0];
 #pragma unroll
-        for (int k = 1; k < 6; k++) v = (lane == k) ? f[k] : v;
-        out[(int64_t)lane * N + I] = v;
-    }
+    for (int k = 0; k < NV; k++)
+        if (k % PG == lane) out[(int64_t)k * N + I] = f[k];
 }
 
-// Diagonal of the initial elastic stiffness, per tet node (t, a) in
-// incidence order: for every facet of tet t at node a, with B_a = [-1, [c^I]x]
-// (a = I) or [1, -[c^J]x] (a = J) and D = E0 (alpha 1 + (1 - alpha) n n^T),
-// (A / l) b_d^T D b_d for each column b_d of B_a.
+// The 6 x 6 block of the initial elastic stiffness that couples a particle's
+// DoFs with themselves, per tet node (t, a) in incidence order: for every
+// facet of tet t at node a, (A / l) G^T D G with G = [-1, [c]x] (c = c^I at
+// the facet's I node, c^J = c^I - l n at its J node, where B_J = -G and the
+// sign cancels) and D = E0 (alpha 1 + (1 - alpha) n n^T).  21 values: the
+// upper triangle row by row, DoFs (u_x, u_y, u_z, th_x, th_y, th_z).
 template <typename R>
-__global__ __launch_bounds__(256) void k_im_diag_k0(const FacetArgs<R> fa, const int32_t* __restrict__ pos, int64_t T,
-                                                    double E0, double alpha, double* __restrict__ out)
+__global__ __launch_bounds__(256) void k_im_block_k0(const FacetArgs<R> fa, const int32_t* __restrict__ pos, int64_t T,
+                                                     double E0, double alpha, double* __restrict__ out)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= 4 * T) return;
     const int64_t t = s >> 2;
     const int a = (int)(s & 3);
     const int64_t F = fa.F;
-    double d[6] = {0, 0, 0, 0, 0, 0};
+    double K[21];
+#pragma unroll
+    for (int p = 0; p < 21; p++) K[p] = 0.0;
     for (int k = 0; k < 12; k++) {
         const int64_t f = t * 12 + k;
         const int32_t rc = fa.rec[f];
@@ -106,25 +110,33 @@ __global__ __launch_bounds__(256) void k_im_diag_k0(const FacetArgs<R> fa, const
         if (aJ == a)
 #pragma unroll
             for (int i = 0; i < 3; i++) c[i] -= len * n[i];
-        const double w = (double)fa.area[f] / len;
-        // translations: b = -+ e_i
+        const double w = (double)fa.area[f] / len * E0;
+        // columns of G: -e_j for the translations, c x e_j for the rotations
+        double g[6][3];
 #pragma unroll
-        for (int i = 0; i < 3; i++) d[i] += w * E0 * (alpha + (1.0 - alpha) * n[i] * n[i]);
-        // rotations: b = +- c x e_i
+        for (int j = 0; j < 3; j++) {
 #pragma unroll
-        for (int i = 0; i < 3; i++) {
-            double b[3] = {0, 0, 0};
-            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
-            b[i1] = c[i2];   // (c x e_i)_{i+1} = c_{i+2}
-            b[i2] = -c[i1];  // (c x e_i)_{i+2} = -c_{i+1}
-            const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-            const double nb = n[0] * b[0] + n[1] * b[1] + n[2] * b[2];
-            d[3 + i] += w * E0 * (alpha * bb + (1.0 - alpha) * nb * nb);
+            for (int i = 0; i < 3; i++) g[j][i] = i == j ? -1.0 : 0.0;
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            g[3 + j][j] = 0.0;
+            g[3 + j][j1] = c[j2];   // (c x e_j)_{j+1} = c_{j+2}
+            g[3 + j][j2] = -c[j1];  // (c x e_j)_{j+2} = -c_{j+1}
         }
-    }
-    const int64_t o = (int64_t)pos[s] * 6;
+        double ng[6];
 #pragma unroll
-    for (int i = 0; i < 6; i++) out[o + i] = d[i];
+        for (int j = 0; j < 6; j++) ng[j] = n[0] * g[j][0] + n[1] * g[j][1] + n[2] * g[j][2];
+        int p = 0;
+#pragma unroll
+        for (int i = 0; i < 6; i++)
+#pragma unroll
+            for (int j = i; j < 6; j++) {
+                const double gg = g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2];
+                K[p++] += w * (alpha * gg + (1.0 - alpha) * ng[i] * ng[j]);
+            }
+    }
+    const int64_t o = (int64_t)pos[s] * 21;
+#pragma unroll
+    for (int p = 0; p < 21; p++) out[o + p] = K[p];
 }
 
 // applied generalised forces of the free DoFs at `time` (zero on prescribed
@@ -271,39 +283,58 @@ __global__ __launch_bounds__(256) void k_im_add(const uint8_t* __restrict__ mode
 }
 
 // ---------------------------------------------------------------------------
-// conjugate gradients on K_eff = cM M + cK K0 over the free DoFs, Jacobi
-// preconditioner; K0 p = -gather(facet kernel of the elastic law at p)
+// conjugate gradients on K_eff = cM M + cK K0 over the free DoFs, block-Jacobi
+// preconditioner (the inverse 6 x 6 particle blocks of K_eff); K0 p = -gather(facet kernel of the elastic law at p)
 // scalars: sc[0] = r.z, sc[1] = alpha_cg, sc[2] = beta_cg, sc[3] = r.r,
 // sc[4] = r.r of the right-hand side, sc[8 + parity] = r.z
 // ---------------------------------------------------------------------------
 struct CgArgs {
     const uint8_t* __restrict__ mode;
     const double* __restrict__ M;
-    const double* __restrict__ diag;  // K_eff diagonal
+    const double* __restrict__ binv;  // [36][N] inverse particle blocks of K_eff (zero on prescribed DoFs)
     double *x, *r, *z, *p, *Ap, *sc, *part;
     double cM, cK;
     int64_t N;
 };
 
-// x = 0, r = R, z = r / diag, p = z; node_p slots = p; partials r.z, r.r
+// z = B^-1 r for one particle (B its block of K_eff; rows of prescribed DoFs
+// are zero, so z vanishes there)
+__device__ __forceinline__ void block_precond(const double* __restrict__ binv, int64_t N, int64_t I,
+                                              const double r[6], double z[6])
+{
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; j++) v += binv[(int64_t)(6 * i + j) * N + I] * r[j];
+        z[i] = v;
+    }
+}
+
+// x = 0, r = R, z = B^-1 r, p = z; node_p slots = p; partials r.z, r.r
+// (one thread per particle, grid-stride)
 __global__ __launch_bounds__(IM_THREADS) void k_cg_init(CgArgs cg, const double* __restrict__ R,
                                                         double* __restrict__ node_p)
 {
     double rz = 0.0, rr = 0.0, zz = 0.0;
-    const int64_t n6 = 6 * cg.N;
+    const int64_t N = cg.N;
     const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
-        const bool fr = cg.mode[i] == 0;
-        const double r = fr ? R[i] : 0.0;
-        const double z = fr ? r / cg.diag[i] : 0.0;
-        cg.x[i] = 0.0;
-        cg.r[i] = r;
-        cg.z[i] = z;
-        cg.p[i] = z;
-        const int64_t c = i / cg.N, pI = i - c * cg.N;
-        node_p[pI * 16 + c] = z;
-        rz += r * z;
-        rr += r * r;
+    for (int64_t I = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; I < N; I += stride) {
+        double r[6], z[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) r[c] = cg.mode[c * N + I] == 0 ? R[c * N + I] : 0.0;
+        block_precond(cg.binv, N, I, r, z);
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            const int64_t i = c * N + I;
+            cg.x[i] = 0.0;
+            cg.r[i] = r[c];
+            cg.z[i] = z[c];
+            cg.p[i] = z[c];
+            node_p[I * 16 + c] = z[c];
+            rz += r[c] * z[c];
+            rr += r[c] * r[c];
+        }
     }
     block_sum3(rz, rr, zz);
     if (threadIdx.x == 0) {
@@ -337,7 +368,8 @@ __global__ __launch_bounds__(IM_THREADS) void k_cg_beta(CgArgs cg, int G, int fi
 // One CG iteration is four kernels: the elastic facet kernel at p, then
 //   k_cg_gather_apply  y = -K0 p per particle, Ap = cM M p - cK y, partials of p.Ap;
 //   k_cg_update        alpha from the p.Ap partials, x += alpha p,
-//                      r -= alpha Ap, z = r / diag, partials of r.z and r.r;
+//                      r -= alpha Ap, z = B^-1 r (particle blocks), partials
+//                      of r.z and r.r;
 //   k_cg_newp          beta from the r.z partials, p = z + beta p.
 // Every block reduces the previous kernel's partials itself, in the same
 // fixed order, so all blocks hold the same scalar and no reduction kernel
@@ -386,7 +418,11 @@ __global__ __launch_bounds__(256) void k_cg_gather_apply(CgArgs cg, const int32_
     if (threadIdx.x == 0) partA[blockIdx.x] = pap;
 }
 
-// alpha = r.z / p.Ap; x += alpha p, r -= alpha Ap, z = r / diag; partials r.z, r.r
+// alpha = r.z / p.Ap; x += alpha p, r -= alpha Ap, z = B^-1 r; partials r.z, r.r.
+// 8 lanes per particle: lane c < 6 updates DoF c and gets the particle's
+// other new residuals by shuffles (no lane reads what another one writes).
+constexpr int CG_LANES = 8;
+
 __global__ __launch_bounds__(IM_THREADS) void k_cg_update(CgArgs cg, const double* __restrict__ partA, int GA,
                                                           double* __restrict__ partB, int par)
 {
@@ -396,17 +432,34 @@ __global__ __launch_bounds__(IM_THREADS) void k_cg_update(CgArgs cg, const doubl
     const double al = pap != 0.0 ? cg.sc[8 + par] / pap : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) cg.sc[1] = al;
     double rz = 0.0, rr = 0.0, u = 0.0;
-    const int64_t n6 = 6 * cg.N;
-    const int64_t stride = (int64_t)gridDim.x * IM_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * IM_THREADS + threadIdx.x; i < n6; i += stride) {
-        if (cg.mode[i] != 0) continue;
-        cg.x[i] += al * cg.p[i];
-        const double r = cg.r[i] - al * cg.Ap[i];
-        const double z = r / cg.diag[i];
-        cg.r[i] = r;
-        cg.z[i] = z;
-        rz += r * z;
-        rr += r * r;
+    const int64_t N = cg.N;
+    constexpr int PER_BLOCK = IM_THREADS / CG_LANES;
+    const int c = (int)(threadIdx.x % CG_LANES);
+    const int base = (int)(threadIdx.x & 63) & ~(CG_LANES - 1);
+    for (int64_t I0 = (int64_t)blockIdx.x * PER_BLOCK; I0 < N; I0 += (int64_t)gridDim.x * PER_BLOCK) {
+        const int64_t I = I0 + threadIdx.x / CG_LANES;
+        const bool act = I < N && c < 6;
+        const int64_t i = (int64_t)c * N + I;
+        double r = 0.0;
+        if (act) {
+            r = cg.r[i];  // zero on prescribed DoFs since k_cg_init
+            if (cg.mode[i] == 0) {
+                cg.x[i] += al * cg.p[i];
+                r -= al * cg.Ap[i];
+            }
+        }
+        double z = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            const double rj = __shfl(r, base + j);
+            if (act) z += cg.binv[(int64_t)(6 * c + j) * N + I] * rj;
+        }
+        if (act) {
+            cg.r[i] = r;
+            cg.z[i] = z;
+            rz += r * z;
+            rr += r * r;
+        }
     }
     block_sum3(rz, rr, u);
     if (threadIdx.x == 0) {
@@ -478,12 +531,80 @@ __global__ __launch_bounds__(256) void k_im_pack(double* __restrict__ node, cons
     node[p * 16 + 6 + c] = v[i];
 }
 
-// diag <- cM M + cK diag(K0)
-__global__ __launch_bounds__(256) void k_im_diag_eff(const double* __restrict__ M, int64_t n6, double cM, double cK,
-                                                     double* __restrict__ diag)
+// Inverse of each particle's 6 x 6 block of K_eff = cM M + cK K0 on its free
+// DoFs (rows and columns of prescribed DoFs replaced by the identity, and
+// zero in the result), by Cholesky; binv[(6 i + j) N + I].  A block that is
+// not positive definite (not expected: K_eff is SPD on the free DoFs) falls
+// back to its inverse diagonal.
+__global__ __launch_bounds__(256) void k_im_block_inv(const double* __restrict__ M, const uint8_t* __restrict__ mode,
+                                                      const double* __restrict__ blk, double cM, double cK,
+                                                      int64_t N, double* __restrict__ binv)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n6) diag[i] = cM * M[i] + cK * diag[i];
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= N) return;
+    bool fr[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++) fr[i] = mode[i * N + I] == 0;
+    double A[6][6];
+    int p = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+#pragma unroll
+        for (int j = i; j < 6; j++) {
+            double v = cK * blk[(int64_t)p * N + I];
+            if (i == j) v += cM * M[i * N + I];
+            if (!fr[i] || !fr[j]) v = i == j ? 1.0 : 0.0;
+            A[i][j] = v;
+            A[j][i] = v;
+            p++;
+        }
+    // A = L L^T, L in the lower triangle of A
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        double d = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; k++) d -= A[j][k] * A[j][k];
+        ok = ok && d > 0.0;
+        const double ljj = sqrt(d > 0.0 ? d : 1.0);
+        A[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < 6; i++) {
+            double v = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; k++) v -= A[i][k] * A[j][k];
+            A[i][j] = v / ljj;
+        }
+    }
+    // columns of the inverse: L y = e_c, L^T x = y
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        double y[6], x[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; k++) v -= A[i][k] * y[k];
+            y[i] = v / A[i][i];
+        }
+#pragma unroll
+        for (int i = 5; i >= 0; i--) {
+            double v = y[i];
+#pragma unroll
+            for (int k = i + 1; k < 6; k++) v -= A[k][i] * x[k];
+            x[i] = v / A[i][i];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            double v = x[i];
+            if (!ok) {
+                const double dg = i == c ? cK * blk[(int64_t)(i * 6 - i * (i - 1) / 2) * N + I] + cM * M[i * N + I]
+                                         : 0.0;
+                v = (i == c && dg > 0.0) ? 1.0 / dg : 0.0;
+            }
+            binv[(int64_t)(6 * i + c) * N + I] = (fr[i] && fr[c]) ? v : 0.0;
+        }
+    }
 }
 
 // a_0 = (g_0 + f_0) / M on free DoFs, 0 on prescribed ones; g_n = g_0;

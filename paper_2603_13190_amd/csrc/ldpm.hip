@@ -132,7 +132,7 @@ struct ldpm_system {
     bool imp_on = false;
     double imp_dt = 0.0, imp_am = 0.0, imp_af = 0.0;
     void* im_mem = nullptr;
-    double *im_q, *im_qn, *im_vn, *im_an, *im_gn, *im_fn, *im_f1, *im_vp, *im_g, *im_R, *im_M, *im_diag;
+    double *im_q, *im_qn, *im_vn, *im_an, *im_gn, *im_fn, *im_f1, *im_vp, *im_g, *im_R, *im_M, *im_binv;
     double *cg_x, *cg_r, *cg_z, *cg_p, *cg_Ap, *cg_sc, *cg_part, *im_red;
     double *im_node_p, *im_ht_scr, *im_wint_scr, *im_con_scr, *im_ht_c, *im_hem_c, *im_wint_c;
 };
@@ -1423,7 +1423,8 @@ hipError_t im_alloc(ldpm_system* s)
     const size_t n6 = 6 * N;
     size_t o[32];
     int k = 0;
-    for (int i = 0; i < 12; i++) o[k++] = cv.take<double>(n6);     // im_* vectors
+    for (int i = 0; i < 11; i++) o[k++] = cv.take<double>(n6);     // im_* vectors
+    o[k++] = cv.take<double>(36 * (size_t)N);                       // inverse particle blocks
     for (int i = 0; i < 5; i++) o[k++] = cv.take<double>(n6);      // cg x r z p Ap
     o[k++] = cv.take<double>(16);                                   // cg_sc
     o[k++] = cv.take<double>(3 * (size_t)IM_MAX_BLOCKS);            // cg_part (partials)
@@ -1442,7 +1443,7 @@ hipError_t im_alloc(ldpm_system* s)
     s->im_mem = mem;
     char* B = (char*)mem;
     double** vec[12] = {&s->im_q, &s->im_qn, &s->im_vn, &s->im_an, &s->im_gn, &s->im_fn, &s->im_f1,
-                        &s->im_vp, &s->im_g, &s->im_R, &s->im_M, &s->im_diag};
+                        &s->im_vp, &s->im_g, &s->im_R, &s->im_M, &s->im_binv};
     k = 0;
     for (int i = 0; i < 12; i++) *vec[i] = (double*)(B + o[k++]);
     double** cgv[5] = {&s->cg_x, &s->cg_r, &s->cg_z, &s->cg_p, &s->cg_Ap};
@@ -1502,7 +1503,7 @@ hipError_t im_cg(ldpm_system* s, double cM, double cK, double tol, int max_it, i
 {
     const int64_t N = s->N;
     const int G = (int)im_blocks(6 * N);
-    CgArgs cg{s->mode, s->im_M, s->im_diag, s->cg_x, s->cg_r, s->cg_z, s->cg_p, s->cg_Ap, s->cg_sc, s->cg_part,
+    CgArgs cg{s->mode, s->im_M, s->im_binv, s->cg_x, s->cg_r, s->cg_z, s->cg_p, s->cg_Ap, s->cg_sc, s->cg_part,
               cM, cK, N};
     hipLaunchKernelGGL(k_cg_init, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)s->im_R, s->im_node_p);
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, G, 1);
@@ -1513,6 +1514,7 @@ hipError_t im_cg(ldpm_system* s, double cM, double cK, double tol, int max_it, i
     const double rr0 = sc[4];
     // partials: p.Ap of the gather-apply grid, then r.z and r.r of the update grid
     const int GA = (int)std::min<int64_t>(IM_MAX_BLOCKS, blocks_for(N * PG, 256));
+    const int GU = (int)std::min<int64_t>(IM_MAX_BLOCKS, blocks_for(N * CG_LANES, IM_THREADS));
     double* partA = s->cg_part;
     double* partB = s->cg_part + IM_MAX_BLOCKS;
     int it = 0, par = 0;
@@ -1521,17 +1523,17 @@ hipError_t im_cg(ldpm_system* s, double cM, double cK, double tol, int max_it, i
             im_k0_facets(s);
             hipLaunchKernelGGL(k_cg_gather_apply<double>, dim3(GA), dim3(256), 0, s->stream, cg,
                                (const int32_t*)s->ptr, (const double*)s->im_con_scr, partA);
-            hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partA, GA,
+            hipLaunchKernelGGL(k_cg_update, dim3(GU), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partA, GA,
                                partB, par);
             it++;
             if (it % 8 == 0 || it == max_it) {
-                hipLaunchKernelGGL(k_cg_rr, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partB, G);
+                hipLaunchKernelGGL(k_cg_rr, dim3(1), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partB, GU);
                 e = hipMemcpyAsync(sc, s->cg_sc, 64, hipMemcpyDeviceToHost, s->stream);
                 if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
                 if (e != hipSuccess) return e;
                 if (!(sc[3] > tol * tol * rr0)) break;
             }
-            hipLaunchKernelGGL(k_cg_newp, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partB, G,
+            hipLaunchKernelGGL(k_cg_newp, dim3(G), dim3(IM_THREADS), 0, s->stream, cg, (const double*)partB, GU,
                                s->im_node_p, par);
             par ^= 1;
         }
@@ -1586,16 +1588,30 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
     const unsigned b6 = blocks_for(n6, 256);
     ImArgs ia{s->mode, s->im_M, s->im_qn, s->im_vn, s->im_an, s->im_gn, s->im_fn, s->im_f1, dt, am, af, be, ga, N};
     if (!s->imp_on) {
-        // committed state from the node records, lumped masses, K_eff diagonal
+        // committed state from the node records, lumped masses, and the
+        // preconditioner: inverse 6 x 6 particle blocks of K_eff (the K0
+        // blocks per tet node and their per-particle sums live in a
+        // temporary buffer)
         hipLaunchKernelGGL(k_im_unpack, dim3(b6), dim3(256), 0, s->stream, (const double*)s->node, N, s->im_qn, s->im_vn);
         for (int d = 0; d < 3; d++) HIP_TRY(hipMemcpyAsync(s->im_M + d * N, s->mass, N * 8, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipMemcpyAsync(s->im_M + 3 * N, s->inertia, 3 * N * 8, hipMemcpyDeviceToDevice, s->stream));
-        hipLaunchKernelGGL(k_im_diag_k0<double>, dim3(blocks_for(4 * T, 256)), dim3(256), 0, s->stream,
-                           facet_args<double>(s), (const int32_t*)s->pos, T, s->matd.E0, s->matd.alpha, s->im_con_scr);
-        hipLaunchKernelGGL(k_im_gather<double>, dim3(blocks_for(N * PG, 256)), dim3(256), 0, s->stream,
-                           (const int32_t*)s->ptr, (const double*)s->im_con_scr, N, s->im_diag);
-        hipLaunchKernelGGL(k_im_diag_eff, dim3(b6), dim3(256), 0, s->stream, (const double*)s->im_M, n6, cM, cK,
-                           s->im_diag);
+        {
+            double* blk = nullptr;
+            const size_t nb = (84 * (size_t)T + 21 * (size_t)N) * 8;
+            if (hipMalloc((void**)&blk, nb) != hipSuccess)
+                return fail(LDPM_ERR_ALLOC, "implicit: hipMalloc(%zu) for the preconditioner failed", nb);
+            double* blk_p = blk + 84 * (size_t)T;
+            hipLaunchKernelGGL(k_im_block_k0<double>, dim3(blocks_for(4 * T, 256)), dim3(256), 0, s->stream,
+                               facet_args<double>(s), (const int32_t*)s->pos, T, s->matd.E0, s->matd.alpha, blk);
+            hipLaunchKernelGGL((k_im_gather<double, 21>), dim3(blocks_for(N * PG, 256)), dim3(256), 0, s->stream,
+                               (const int32_t*)s->ptr, (const double*)blk, N, blk_p);
+            hipLaunchKernelGGL(k_im_block_inv, dim3(blocks_for(N, 256)), dim3(256), 0, s->stream,
+                               (const double*)s->im_M, s->mode, (const double*)blk_p, cM, cK, N, s->im_binv);
+            hipError_t eb = hipGetLastError();
+            if (eb == hipSuccess) eb = hipStreamSynchronize(s->stream);
+            (void)hipFree(blk);
+            if (eb != hipSuccess) return fail(LDPM_ERR_DEVICE, "implicit: preconditioner: %s", hipGetErrorString(eb));
+        }
         HIP_TRY(hipMemcpyAsync(s->im_node_p, s->node, 16 * N * 8, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipMemsetAsync(s->cg_Ap, 0, n6 * 8, s->stream));
         hipLaunchKernelGGL(k_im_nodes, dim3(b6), dim3(256), 0, s->stream, s->im_node_p, (const double*)s->cg_Ap, nullptr, N);
