@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from typing import Optional
 
 import numpy as np
@@ -222,7 +223,10 @@ class _TorchAllocator:
         def _free(ptr, ctx):
             if ptr in self.live:
                 del self.live[ptr]
-                torch.cuda.caching_allocator_delete(ptr)
+                # a handle collected while the interpreter shuts down finds
+                # torch already torn down; the process releases the memory
+                if not sys.is_finalizing():
+                    torch.cuda.caching_allocator_delete(ptr)
 
         self.c_alloc = ALLOC_FN(_alloc)
         self.c_free = FREE_FN(_free)
