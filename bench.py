@@ -41,6 +41,12 @@ def make_workload(name):
         s = S.batch_sliding_compression(64, seed=0)
         return s, ("64 x unconfined compression, sliding platens, edge U(50,100) mm, d 4-8 mm, "
                    "strain rate 2.5e-2 /s, seeds 0..63 (one batched system)"), 2000
+    # the two large single specimens, selectable for profiling runs
+    if name == "confined150":
+        return gen_confined150(), ("confined compression, 150 mm cube, d 4-12 mm, seed 1, 20 MPa lateral "
+                                   "pressure then axial shortening"), 2000
+    if name == "cylinder_full":
+        return gen_cylinder(1.1), "cylinder 100 x 200 mm, d 1.1-2.2 mm, seed 1, tension-compression cycles", 2000
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -575,12 +581,14 @@ def surrogate_case(args, sysd_tension, tune):
     return rec, model
 
 
-def window_case(sysd, workload, runs, warmup, steps, tune, field=None):
+def window_case(sysd, workload, runs, warmup, steps, tune, field=None, key=None):
     """Throughput of `steps` explicit steps after `warmup` steps from the
     initial state, per precision (and with the surrogate when a model is
     given), with the facet kernel's HBM rate from HIP-event kernel times.
     field ("crack" or "volumetric"): the runs' end fields are compared
-    pairwise as the paper compares solutions (Pearson, NRMSE)."""
+    pairwise as the paper compares solutions (Pearson, NRMSE).  key: the
+    workload's name in profiles/ for the FP64 facet kernel's measured HBM
+    traffic (reported while the kernel sources are unchanged)."""
     import torch
     from paper_2603_13190_amd.ldpm import System
     m = sysd["meta"]
@@ -614,6 +622,10 @@ def window_case(sysd, workload, runs, warmup, steps, tune, field=None):
             r.update(facet_kernel_avg_us=favg * 1e3,
                      facet_kernel_GBs=info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9,
                      facet_kernel_frac_hbm=info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9 / PEAK_HBM_GBS)
+            if prec == "fp64" and key:
+                kname = "k_facet<double, 1, %d, 0>" % g.get_launch()["tets_per_block"]
+                r["facet_kernel_alg_bytes"] = info["facet_kernel_bytes"]
+                r["facet_kernel_traffic"] = measured_traffic(key, kname)
         else:
             r["surrogate_share_of_facets_at_end"] = 1.0 - g.surrogate_count() / F
         if field == "crack":
@@ -836,7 +848,7 @@ def main():
             return window_case(
                 conf, "confined compression, 150 mm cube, d 4-12 mm, seed 1, 20 MPa lateral pressure "
                       "then axial shortening", [("fp64", "fp64", None), ("mixed", "mixed", None)],
-                2000, args.large_steps, tune, field="volumetric")
+                2000, args.large_steps, tune, field="volumetric", key="confined150")
 
         def cylinder():
             cyl = futs["cylinder"].result()
@@ -845,7 +857,8 @@ def main():
                 runs.append(("surrogate", "mixed", model))
             return window_case(
                 cyl, f"cylinder 100 x 200 mm, d {args.cyl_full_d0:g}-{2 * args.cyl_full_d0:g} mm, seed 1, "
-                     "window in the first tension leg", runs, 3000, args.large_steps, tune, field="crack")
+                     "window in the first tension leg", runs, 3000, args.large_steps, tune, field="crack",
+                key="cylinder_full" if args.cyl_full_d0 == 1.1 else None)
         for name, fn in (("confined150", confined), ("cylinder_full", cylinder)):
             r = optional(name, fn)
             if r is not None:
