@@ -578,8 +578,9 @@ class TessOut(C.Structure):
 def tessellate(x, diam, tets, rho, cones=False, stream=None):
     """LDPM facets and cell mass properties from centres x (N, 3), diameters
     (N,), tetrahedra (T, 4) and density rho, computed on the GPU
-    (ldpm_tessellate).  Returns the generator layout: facet arrays (F,) /
-    (F, 3) in tet-major order, mass (N,), inertia (N, 3) (diagonal of J),
+    (ldpm_tessellate).  Returns the generator layout (the (F, 3) and (N, 3)
+    arrays as transposed views): facet arrays (F,) / (F, 3) in tet-major
+    order, mass (N,), inertia (N, 3) (diagonal of J),
     cell_inertia (N, 3, 3), cell_vol (N,), cell_r (N, 3); with cones=True
     also tet_node_cones (T, 4, 10)."""
     import torch  # noqa: F401  (HIP runtime and stream provider)
@@ -611,11 +612,14 @@ def tessellate(x, diam, tets, rho, cones=False, stream=None):
     for p, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2))):
         Jf[:, i, j] = J6[p]
         Jf[:, j, i] = J6[p]
+    # (F, 3) and (N, 3) arrays are transposed views of the library's [3][F]
+    # and [3][N] outputs: no copy, and the loader's structure-of-arrays
+    # conversion of a view is the original array again
     res = dict(facet_I=out["facet_I"], facet_J=out["facet_J"],
-               facet_cI=out["facet_cI"].T.copy(), facet_n=out["facet_n"].T.copy(), facet_m=out["facet_m"].T.copy(),
+               facet_cI=out["facet_cI"].T, facet_n=out["facet_n"].T, facet_m=out["facet_m"].T,
                facet_area=out["facet_area"], facet_area0=out["facet_area0"], facet_len=out["facet_len"],
-               mass=out["mass"], inertia=out["rot_inertia"].T.copy(), cell_inertia=Jf, cell_vol=out["cell_vol"],
-               cell_r=out["cell_r"].T.copy())
+               mass=out["mass"], inertia=out["rot_inertia"].T, cell_inertia=Jf, cell_vol=out["cell_vol"],
+               cell_r=out["cell_r"].T)
     if cones:
         res["tet_node_cones"] = cone
     return res
