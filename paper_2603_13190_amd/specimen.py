@@ -37,6 +37,7 @@ Units: mm, N, MPa, s, tonne (density 2.4e-9 t/mm^3).
 """
 from __future__ import annotations
 
+import ctypes as C
 import dataclasses
 import hashlib
 import math
@@ -248,18 +249,50 @@ def surface_nodes(shape: Shape, d0, rng, spacing=1.4, jitter=0.1):
 
 
 def place_particles(shape: Shape, d0, da, rng, gap=0.1, nF=0.4, max_tries=200,
-                    vol_fraction=None):
+                    vol_fraction=None, native=None):
     """Random sequential addition of Fuller-distributed particles.
 
     Returns (centres (n,3), diameters (n,)) of interior particles, placed so
     that they keep the minimum gap from each other and from the surface
-    nodes (distance to the surface >= r + d0/2 (1 + gap))."""
+    nodes (distance to the surface >= r + d0/2 (1 + gap)).  Every particle
+    draws its max_tries candidates at once, so the random stream does not
+    depend on which are accepted.  native (None: when available): the
+    acceptance loop in C (gen/placement.c), which accepts exactly the same
+    candidates as the Python loop."""
     if vol_fraction is None:
         vol_fraction = aggregate_fraction() * (1.0 - (d0 / da) ** nF)
     d = fuller_diameters(rng, vol_fraction * shape.volume(), d0, da, nF)
     d = np.sort(d)[::-1]
-    grid = _Grid(da * (1.0 + gap))
+    cell = da * (1.0 + gap)
+    L = None
+    if native is not False:
+        from . import gen
+        L = gen.lib()
+        if L is None and native:
+            raise RuntimeError("the native placement library could not be built")
     xs, ds = [], []
+    if L is not None:
+        ext = shape.size if shape.kind == "box" else (shape.size[0], shape.size[0], shape.size[1])
+        h = L.place_create(cell, float(ext[0]), float(ext[1]), float(ext[2]), int(d.size))
+        if not h:
+            raise MemoryError("placement grid")
+        try:
+            for di in d:
+                r = 0.5 * di
+                margin = r + 0.5 * d0 * (1.0 + gap) + gap * d0
+                cand = np.ascontiguousarray(shape.sample_inside(rng, margin, max_tries), dtype=np.float64)
+                if cand.shape[0] == 0:
+                    continue
+                k = L.place_try(h, cand.ctypes.data_as(C.POINTER(C.c_double)), cand.shape[0], r, gap)
+                if k == -2:
+                    raise RuntimeError("placement grid overflow")
+                if k >= 0:
+                    xs.append(cand[k])
+                    ds.append(di)
+        finally:
+            L.place_free(h)
+        return np.array(xs, dtype=float).reshape(-1, 3), np.array(ds, dtype=float)
+    grid = _Grid(cell)
     for di in d:
         r = 0.5 * di
         margin = r + 0.5 * d0 * (1.0 + gap) + gap * d0
