@@ -354,22 +354,31 @@ def peel_boundary_slivers(x, tets, is_surf, qmin=0.05, max_iter=50):
     """Remove, layer by layer, boundary tetrahedra whose four nodes all lie on
     the specimen surface and whose quality is below qmin: the Delaunay
     tetrahedralisation of points on a curved surface leaves thin slivers
-    spanning the hull."""
+    spanning the hull.  Each layer removes, at once, every such tetrahedron
+    with a face that no other remaining tetrahedron shares.  Only the fixed
+    set of surface-only low-quality tetrahedra can ever go, so the face
+    multiplicities are counted once and decremented as tetrahedra are
+    removed."""
+    T = tets.shape[0]
+    if T == 0:
+        return tets
+    faces = np.concatenate([np.sort(tets[:, [b for b in range(4) if b != miss]], axis=1)
+                            for miss in range(4)])
+    _, inv, cnt = np.unique(_triple_key(faces, x.shape[0]), return_inverse=True, return_counts=True)
+    face_of = inv.ravel().reshape(4, T)          # unique face id of face `miss` of tet t
+    alive = np.ones(T, bool)
+    cand = np.flatnonzero(is_surf[tets].all(axis=1) & (tet_quality(x, tets) < qmin))
     for _ in range(max_iter):
-        if tets.shape[0] == 0:
+        if not alive.any() or cand.size == 0:
             break
-        faces = np.concatenate([np.sort(tets[:, [b for b in range(4) if b != miss]], axis=1)
-                                for miss in range(4)])
-        tid = np.tile(np.arange(tets.shape[0]), 4)
-        _, inv, cnt = np.unique(_triple_key(faces, x.shape[0]), return_inverse=True, return_counts=True)
-        on_bnd = np.zeros(tets.shape[0], bool)
-        on_bnd[tid[cnt[inv.ravel()] == 1]] = True
-        all_surf = is_surf[tets].all(axis=1)
-        bad = on_bnd & all_surf & (tet_quality(x, tets) < qmin)
-        if not bad.any():
+        on_bnd = (cnt[face_of[:, cand]] == 1).any(axis=0)
+        bad = cand[on_bnd]
+        if bad.size == 0:
             break
-        tets = tets[~bad]
-    return tets
+        alive[bad] = False
+        np.subtract.at(cnt, face_of[:, bad].ravel(), 1)
+        cand = cand[~on_bnd]
+    return tets[alive]
 
 
 def frame_from_normal(n):
