@@ -649,7 +649,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     const size_t o_pos = cv.take<int32_t>(4 * T);
     const size_t o_rec = cv.take<int32_t>(F), o_flag = cv.take<int32_t>(4), o_bar = cv.take<unsigned>(4);
     const size_t o_poff = cv.take<int64_t>(nP + 1), o_pt = cv.take<double>(npts + 1), o_pv = cv.take<double>(npts + 1);
-    const size_t o_red = cv.take<double>(8);
+    const size_t o_red = cv.take<double>(8 + 3 * RED_MAX_BLOCKS);  // results, then reduction partials
     const size_t o_mblk = mblk.empty() ? 0 : cv.take<double>(72 * N);
     const size_t o_progv = cv.take<double>(2 * nP + 2);
     cv.off = (cv.off + 255) & ~size_t(255);
@@ -901,12 +901,24 @@ ldpm_status ldpm_read_state(ldpm_system* s, ldpm_state* o)
     return st;
 }
 
+// grid of the two-stage reductions: one block per RED_THREADS elements, at most RED_MAX_BLOCKS
+static int red_blocks(int64_t n)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>(RED_MAX_BLOCKS, (n + RED_THREADS - 1) / RED_THREADS));
+}
+
 ldpm_status ldpm_energy(ldpm_system* s, int32_t sp, ldpm_energies* o)
 {
     if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
     if (sp < 0 || sp >= s->nspec) return fail(LDPM_ERR_ARG, "specimen %d out of range", sp);
-    hipLaunchKernelGGL(k_energy, dim3(1), dim3(RED_THREADS), 0, s->stream, s->wint, s->toff[sp], s->toff[sp + 1],
-                       s->wext, s->wkin, s->poff[sp], s->poff[sp + 1], s->red);
+    {
+        const int64_t n = std::max(s->toff[sp + 1] - s->toff[sp], s->poff[sp + 1] - s->poff[sp]);
+        const int G = red_blocks(n);
+        hipLaunchKernelGGL(k_energy_part, dim3(G), dim3(RED_THREADS), 0, s->stream, s->wint, s->toff[sp],
+                           s->toff[sp + 1], s->wext, s->wkin, s->poff[sp], s->poff[sp + 1], s->red + 8);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RED_THREADS), 0, s->stream, (const double*)(s->red + 8), G, 3,
+                           s->red);
+    }
     HIP_TRY(hipGetLastError());
     ldpm_status st = ldpm_sync(s);
     if (st != LDPM_OK && st != LDPM_ERR_UNSTABLE) return st;
@@ -927,8 +939,13 @@ ldpm_status ldpm_energy(ldpm_system* s, int32_t sp, ldpm_energies* o)
 ldpm_status ldpm_reaction(ldpm_system* s, int32_t program, double* out)
 {
     if (!s || !out) return fail(LDPM_ERR_ARG, "null argument");
-    hipLaunchKernelGGL(k_reaction, dim3(1), dim3(RED_THREADS), 0, s->stream, s->fext, s->prog, 6 * s->N, program,
-                       s->red + 4);
+    {
+        const int G = red_blocks(6 * s->N);
+        hipLaunchKernelGGL(k_reaction_part, dim3(G), dim3(RED_THREADS), 0, s->stream, s->fext, s->prog, 6 * s->N,
+                           program, s->red + 8);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RED_THREADS), 0, s->stream, (const double*)(s->red + 8), G, 1,
+                           s->red + 4);
+    }
     HIP_TRY(hipGetLastError());
     ldpm_status st = ldpm_sync(s);
     if (st != LDPM_OK && st != LDPM_ERR_UNSTABLE) return st;

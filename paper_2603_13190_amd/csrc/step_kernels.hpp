@@ -784,14 +784,23 @@ __device__ double block_sum_fixed(double x)
     return r;
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_energy(const double* __restrict__ wint, int64_t t0,
-                                                        int64_t t1, const double* __restrict__ wext,
-                                                        const double* __restrict__ wkin, int64_t p0,
-                                                        int64_t p1, double* __restrict__ out)
+// Two stages with fixed grids: block b of G sums the elements
+// lo + b*RED_THREADS + k*G*RED_THREADS (thread order, then the LDS tree)
+// into partials [3][G]; one block then adds the G partials in order.  G
+// depends only on the range's own length, so a specimen's energies do not
+// depend on the other specimens of a batch.
+constexpr int RED_MAX_BLOCKS = 1024;
+
+__global__ __launch_bounds__(RED_THREADS) void k_energy_part(const double* __restrict__ wint, int64_t t0,
+                                                             int64_t t1, const double* __restrict__ wext,
+                                                             const double* __restrict__ wkin, int64_t p0,
+                                                             int64_t p1, double* __restrict__ part)
 {
+    const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+    const int64_t o = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t i = t0 + threadIdx.x; i < t1; i += RED_THREADS) a += wint[i];
-    for (int64_t i = p0 + threadIdx.x; i < p1; i += RED_THREADS) {
+    for (int64_t i = t0 + o; i < t1; i += stride) a += wint[i];
+    for (int64_t i = p0 + o; i < p1; i += stride) {
         b += wext[i];
         c += wkin[i];
     }
@@ -799,20 +808,34 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy(const double* __restrict
     b = block_sum_fixed(b);
     c = block_sum_fixed(c);
     if (threadIdx.x == 0) {
-        out[0] = a;
-        out[1] = b;
-        out[2] = c;
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+        part[2 * gridDim.x + blockIdx.x] = c;
     }
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_reaction(const double* __restrict__ fext,
-                                                          const int32_t* __restrict__ prog, int64_t n6,
-                                                          int32_t p, double* __restrict__ out)
+// resultant of the generalised forces of DoFs driven by program p (partials)
+__global__ __launch_bounds__(RED_THREADS) void k_reaction_part(const double* __restrict__ fext,
+                                                               const int32_t* __restrict__ prog, int64_t n6,
+                                                               int32_t p, double* __restrict__ part)
 {
+    const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
     double a = 0.0;
-    for (int64_t i = threadIdx.x; i < n6; i += RED_THREADS)
+    for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n6; i += stride)
         if (prog[i] == p) a += fext[i];
     a = block_sum_fixed(a);
-    if (threadIdx.x == 0) out[0] = a;
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+// out[k] = sum of part[k*G .. k*G + G) in order, k < nk (one block)
+__global__ __launch_bounds__(RED_THREADS) void k_sum_parts(const double* __restrict__ part, int G, int nk,
+                                                           double* __restrict__ out)
+{
+    for (int k = 0; k < nk; k++) {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < G; i += RED_THREADS) a += part[(int64_t)k * G + i];
+        a = block_sum_fixed(a);
+        if (threadIdx.x == 0) out[k] = a;
+    }
 }
 
