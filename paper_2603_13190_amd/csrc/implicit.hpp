@@ -283,8 +283,9 @@ __global__ __launch_bounds__(256) void k_im_add(const uint8_t* __restrict__ mode
 }
 
 // ---------------------------------------------------------------------------
-// conjugate gradients on K_eff = cM M + cK K0 over the free DoFs, block-Jacobi
-// preconditioner (the inverse 6 x 6 particle blocks of K_eff); K0 p = -gather(facet kernel of the elastic law at p)
+// conjugate gradients on K_eff = cM M + cK K0 over the free DoFs with a
+// block-Jacobi preconditioner (the inverse 6 x 6 particle blocks of K_eff);
+// K0 p = -gather(facet kernel of the elastic law at p)
 // scalars: sc[0] = r.z, sc[1] = alpha_cg, sc[2] = beta_cg, sc[3] = r.r,
 // sc[4] = r.r of the right-hand side, sc[8 + parity] = r.z
 // ---------------------------------------------------------------------------
