@@ -160,3 +160,14 @@ def test_specimen_builder_with_device_geometry():
     for k in FLOAT_KEYS + ("dof_scale",):
         a, b = np.asarray(g[k]), np.asarray(h[k], np.float64)
         assert np.abs(a - b).max() <= TOL * max(np.abs(b).max(), 1e-300), k
+
+
+@pytest.mark.gpu
+def test_cylinder_geometry_matches_the_generator():
+    """The d 2-4 mm cylinder (2.27M facets, the largest specimen the GPU
+    tests build): every facet and cell against the input generator's
+    arrays, which the oracle's pins tie to the oracle at 1e-13."""
+    from tests.gpu_util import cylinder_full
+    s = cylinder_full()
+    g = ldpm.tessellate(s["x0"], s["diam"], s["tet_nodes"], S.RHO)
+    _compare(g, {k: s[k] for k in ("facet_I", "facet_J") + FLOAT_KEYS})
