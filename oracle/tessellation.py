@@ -24,9 +24,11 @@ documents:
   centre to the facet triangles; volume, first and second moments are the
   exact cone integrals, signed by whether the triangle faces away from the
   centre (outward normal of the I cell is +n, of the J cell -n).
-Returns per facet (tet-major) I, J, cI, n, m, A, A0, l and per particle
+Returns per facet (tet-major) I, J, cI, n, m, A, A0, l, per particle
 mass, the diagonal and full inertia tensors about the centre, volume and
-centroid offset.
+centroid offset, and per tetrahedron its share of its four nodes' lumped
+masses (T, 4, 6: rho V three times, then the diagonal of rho (tr S - S) of
+its cones).
 """
 from __future__ import annotations
 
@@ -78,6 +80,8 @@ def tessellate(x, diam, tets, rho):
     vol = np.zeros(N)
     mom1 = np.zeros((N, 3))
     mom2 = np.zeros((N, 3, 3))
+    share = np.zeros((T, 4, 6))   # each tetrahedron's part of its nodes' lumped masses
+    rows = np.arange(T)
     for k, (a, b, c) in enumerate(_facet_list()):
         d = 6 - a - b - c                     # the node missing from face (a, b, c)
         P0, P1, P2 = ep[(a, b)], fp[d], tp
@@ -97,7 +101,7 @@ def tessellate(x, diam, tets, rho):
         # cone (centre, triangle) integrals for the two cells; the triangle
         # P0, P1, P2 winds about +n when orient = +1
         orient = np.sign((np.cross(P1 - P0, P2 - P0) * av).sum(1))
-        for side, node in ((1.0, Ii), (-1.0, Jj)):
+        for side, node, loc in ((1.0, Ii, np.where(ga < gb, a, b)), (-1.0, Jj, np.where(ga < gb, b, a))):
             o = x[node]
             q1, q2, q3 = P0 - o, P1 - o, P2 - o
             V = side * orient * (np.cross(q1, q2) * q3).sum(1) / 6.0
@@ -107,6 +111,9 @@ def tessellate(x, diam, tets, rho):
             np.add.at(vol, node, V)
             np.add.at(mom1, node, V[:, None] * ssum / 4.0)
             np.add.at(mom2, node, S)
+            dS = np.einsum("tii->ti", S)
+            share[rows, loc, 0:3] += (rho * V)[:, None]
+            share[rows, loc, 3:6] += rho * (dS.sum(1)[:, None] - dS)
     n_f = nn.reshape(F, 3)
     ax = np.argmin(np.abs(n_f), axis=1)
     e = np.zeros_like(n_f)
@@ -118,4 +125,4 @@ def tessellate(x, diam, tets, rho):
     return dict(facet_I=I.reshape(F), facet_J=J.reshape(F), facet_cI=cI.reshape(F, 3), facet_n=n_f,
                 facet_m=m, facet_area=A.reshape(F), facet_area0=A0.reshape(F), facet_len=Ln.reshape(F),
                 mass=rho * vol, inertia=np.ascontiguousarray(np.einsum("nii->ni", Jfull)), cell_inertia=Jfull,
-                cell_vol=vol, cell_r=mom1 / np.maximum(vol, 1e-300)[:, None])
+                cell_vol=vol, cell_r=mom1 / np.maximum(vol, 1e-300)[:, None], tet_node_share=share)
