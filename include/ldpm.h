@@ -488,6 +488,31 @@ typedef struct {
 } ldpm_tess_out;
 ldpm_status ldpm_tessellate(const ldpm_tess_desc *desc, ldpm_tess_out *out, void *stream);
 
+/* ---- Element bound of the stable explicit step --------------------------
+ * The paper sets the explicit step from an eigenvalue analysis of each
+ * tetrahedron (section on free vibrations in the linear elastic regime):
+ * lam[t] = largest eigenvalue of W K_e W for tetrahedron t, with K_e the
+ * elastic stiffness of its 12 facets, sum (A/l) B^T D B, B = [-1, [c^I]x]
+ * at the facet's I node and [1, -[c^J]x] at its J node (eq. strain1,
+ * c^J = c^I - l n), D = E0 (alpha 1 + (1 - alpha) n n^T), and W =
+ * diag(share)^(-1/2) from the tetrahedron's share of its four nodes' lumped
+ * masses.  max_t lam[t] bounds the assembled system's largest eigenvalue;
+ * dt = fraction * 2 / sqrt(max lam).  Facets tet-major (facet 12 t + k of
+ * tetrahedron t), each joining two nodes of its tetrahedron.  DoF order per
+ * node (u_x, u_y, u_z, th_x, th_y, th_z).  HOST arrays owned by the caller;
+ * runs on `stream`, allocates and frees its device buffers, synchronises.
+ * Errors: LDPM_ERR_ARG for inconsistent or non-finite input. */
+typedef struct {
+    int64_t n_particles, n_tets;
+    const int32_t *tet_nodes;                 /* [4][T] */
+    const int32_t *facet_I, *facet_J;         /* [F], F = 12 T */
+    const double *facet_cI, *facet_n;         /* [3][F] */
+    const double *facet_area, *facet_len;     /* [F] */
+    const double *share;                      /* [T][4][6] (> 0) */
+    double E0, alpha;
+} ldpm_elem_desc;
+ldpm_status ldpm_element_lambda(const ldpm_elem_desc *desc, double *lam, void *stream);
+
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);
 

@@ -86,6 +86,7 @@ ldpm_status ldpm_fail(ldpm_status st, const char* fmt, ...)
 #include "fields.hpp"
 #include "implicit.hpp"
 #include "tessellate.hpp"
+#include "bound.hpp"
 
 // ---------------------------------------------------------------------------
 // host side
@@ -1800,6 +1801,77 @@ ldpm_status ldpm_tessellate(const ldpm_tess_desc* d, ldpm_tess_out* o, void* str
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(mem);
     if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "tessellate failed: %s", hipGetErrorString(e));
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_element_lambda(const ldpm_elem_desc* d, double* lam, void* stream)
+{
+    if (!d || !lam || !d->tet_nodes || !d->facet_I || !d->facet_J || !d->facet_cI || !d->facet_n ||
+        !d->facet_area || !d->facet_len || !d->share)
+        return fail(LDPM_ERR_ARG, "null argument");
+    const int64_t N = d->n_particles, T = d->n_tets, F = 12 * T;
+    if (N <= 0 || T <= 0) return fail(LDPM_ERR_ARG, "element bound: empty input");
+    if (N >= (1ll << 31) || F >= (1ll << 31)) return fail(LDPM_ERR_ARG, "element bound: too large for 32-bit ids");
+    if (!(d->E0 > 0) || !std::isfinite(d->E0) || !(d->alpha >= 0) || !std::isfinite(d->alpha))
+        return fail(LDPM_ERR_ARG, "element bound: need E0 > 0 and alpha >= 0");
+    if (!finite_all(d->facet_cI, 3 * F) || !finite_all(d->facet_n, 3 * F) || !finite_all(d->facet_area, F))
+        return fail(LDPM_ERR_ARG, "element bound: non-finite facet data");
+    for (int64_t f = 0; f < F; f++)
+        if (!(d->facet_len[f] > 0) || !std::isfinite(d->facet_len[f]))
+            return fail(LDPM_ERR_ARG, "element bound: facet %lld: length must be positive", (long long)f);
+    for (int64_t i = 0; i < 24 * T; i++)
+        if (!(d->share[i] > 0) || !std::isfinite(d->share[i]))
+            return fail(LDPM_ERR_ARG, "element bound: mass shares must be positive");
+    for (int64_t t = 0; t < T; t++) {
+        int32_t id[4];
+        for (int a = 0; a < 4; a++) {
+            id[a] = d->tet_nodes[a * T + t];
+            if (id[a] < 0 || id[a] >= N) return fail(LDPM_ERR_ARG, "element bound: tet %lld: node out of range", (long long)t);
+        }
+        for (int k = 0; k < 12; k++) {
+            const int32_t I = d->facet_I[t * 12 + k], J = d->facet_J[t * 12 + k];
+            bool hi = false, hj = false;
+            for (int a = 0; a < 4; a++) {
+                hi = hi || id[a] == I;
+                hj = hj || id[a] == J;
+            }
+            if (!hi || !hj || I == J)
+                return fail(LDPM_ERR_ARG, "element bound: facet %lld does not join two nodes of its tet",
+                            (long long)(t * 12 + k));
+        }
+    }
+    Carve cv;
+    const size_t o_tet = cv.take<int32_t>(4 * T), o_I = cv.take<int32_t>(F), o_J = cv.take<int32_t>(F);
+    const size_t o_cI = cv.take<double>(3 * F), o_n = cv.take<double>(3 * F), o_A = cv.take<double>(F);
+    const size_t o_len = cv.take<double>(F), o_sh = cv.take<double>(24 * T), o_lam = cv.take<double>(T);
+    const size_t bytes = (cv.off + 255) & ~size_t(255);
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return fail(LDPM_ERR_ALLOC, "element bound: hipMalloc(%zu) failed", bytes);
+    char* B = (char*)mem;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    auto up = [&](size_t off, const void* src, size_t nb) {
+        if (e == hipSuccess) e = hipMemcpyAsync(B + off, src, nb, hipMemcpyHostToDevice, st);
+    };
+    up(o_tet, d->tet_nodes, 4 * T * 4);
+    up(o_I, d->facet_I, F * 4);
+    up(o_J, d->facet_J, F * 4);
+    up(o_cI, d->facet_cI, 3 * F * 8);
+    up(o_n, d->facet_n, 3 * F * 8);
+    up(o_A, d->facet_area, F * 8);
+    up(o_len, d->facet_len, F * 8);
+    up(o_sh, d->share, 24 * T * 8);
+    if (e == hipSuccess) {
+        ElemIn in{(const int32_t*)(B + o_tet), (const int32_t*)(B + o_I), (const int32_t*)(B + o_J),
+                  (const double*)(B + o_cI), (const double*)(B + o_n), (const double*)(B + o_A),
+                  (const double*)(B + o_len), (const double*)(B + o_sh), d->E0, d->alpha, T};
+        hipLaunchKernelGGL(k_elem_lambda, dim3(blocks_for(T, EB_WAVES)), dim3(256), 0, st, in, (double*)(B + o_lam));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(lam, B + o_lam, T * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "element bound failed: %s", hipGetErrorString(e));
     return LDPM_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
            "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_capture_begin",
            "ldpm_capture_end", "ldpm_crack_opening", "ldpm_volumetric_strain", "ldpm_compare_fields",
-           "ldpm_perturb", "ldpm_implicit_step", "ldpm_tessellate",
+           "ldpm_perturb", "ldpm_implicit_step", "ldpm_tessellate", "ldpm_element_lambda",
            "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
@@ -155,6 +155,7 @@ def lib():
         L.ldpm_autotune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Launch), _dp,
                                     C.POINTER(TuneTrial), C.c_int32, C.POINTER(C.c_int32)]
         L.ldpm_tessellate.argtypes = [C.POINTER(TessDesc), C.POINTER(TessOut), C.c_void_p]
+        L.ldpm_element_lambda.argtypes = [C.POINTER(ElemDesc), _dp, C.c_void_p]
         L.ldpm_mlp_num_params.restype = C.c_int32
         L.ldpm_mlp_create.argtypes = [_fp, C.c_void_p, C.POINTER(C.c_void_p)]
         L.ldpm_mlp_set_data.argtypes = [C.c_void_p, _fp, _fp, C.c_int64]
@@ -623,6 +624,33 @@ def tessellate(x, diam, tets, rho, cones=False, stream=None):
     if cones:
         res["tet_node_cones"] = cone
     return res
+
+
+class ElemDesc(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("n_tets", C.c_int64), ("tet_nodes", _ip), ("facet_I", _ip),
+                ("facet_J", _ip), ("facet_cI", _dp), ("facet_n", _dp), ("facet_area", _dp), ("facet_len", _dp),
+                ("share", _dp), ("E0", C.c_double), ("alpha", C.c_double)]
+
+
+def element_lambda_max(sysd, E0, alpha, share, stream=None):
+    """Largest eigenvalue of each tetrahedron's mass-scaled elastic stiffness
+    (ldpm_element_lambda) for a generator dict (facets tet-major) and the
+    tetrahedra's mass shares (T, 4, 6).  Returns (T,)."""
+    import torch  # noqa: F401  (HIP runtime and stream provider)
+    x = np.asarray(sysd["x0"])
+    tets = np.asarray(sysd["tet_nodes"])
+    N, T = x.shape[0], tets.shape[0]
+    k = dict(tn=_soa(tets, np.int32), fI=_soa(sysd["facet_I"], np.int32), fJ=_soa(sysd["facet_J"], np.int32),
+             cI=_soa(sysd["facet_cI"]), n=_soa(sysd["facet_n"]), A=_soa(sysd["facet_area"]),
+             L=_soa(sysd["facet_len"]), sh=np.ascontiguousarray(share, dtype=np.float64))
+    if k["sh"].shape != (T, 4, 6):
+        raise ValueError("share must be (T, 4, 6)")
+    d = ElemDesc(N, T, _p(k["tn"], _ip), _p(k["fI"], _ip), _p(k["fJ"], _ip), _p(k["cI"], _dp), _p(k["n"], _dp),
+                 _p(k["A"], _dp), _p(k["L"], _dp), _p(k["sh"], _dp), float(E0), float(alpha))
+    lam = np.empty(T)
+    st = C.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib().ldpm_element_lambda(C.byref(d), _p(lam, _dp), st))
+    return lam
 
 
 class Mlp:

@@ -710,8 +710,15 @@ def build_geometry(shape: Shape, d0, da, seed, gap=0.1, rho=RHO, vol_fraction=No
     return sysd
 
 
-def stable_dt(sysd, mat, fraction=0.8):
-    lam = element_lambda_max(sysd, mat["E0"], mat["alpha"])
+def stable_dt(sysd, mat, fraction=0.8, device=False):
+    """fraction x 2 / sqrt(max element eigenvalue); the element eigenvalues
+    on the host (LAPACK) or, with device=True, on the GPU
+    (ldpm_element_lambda)."""
+    if device:
+        from . import ldpm
+        lam = ldpm.element_lambda_max(sysd, mat["E0"], mat["alpha"], sysd["_elem_mass"])
+    else:
+        lam = element_lambda_max(sysd, mat["E0"], mat["alpha"])
     return fraction * 2.0 / math.sqrt(lam.max()), lam
 
 
@@ -776,7 +783,7 @@ def elastic_vibration_cube(edge=50.0, d0=4.0, da=8.0, seed=1, v0_amp=10.0,
     v0 = np.zeros((N, 6))
     v0[:, 0] = v0_amp * np.sin(np.pi * x[:, 2] / (2 * edge))
     v0[faces["zmin"]] = 0.0
-    dt, lam = stable_dt(g, mat, dt_fraction)
+    dt, lam = stable_dt(g, mat, dt_fraction, device=device)
     return finalize(g, mat, mode, prog, scale, Programs(), v0, dt,
                     f"elastic_cube{edge:g}_s{seed}",
                     dict(d0=d0, da=da, seed=seed, lam_max=float(lam.max()),
@@ -805,7 +812,7 @@ def tension_cube(edge=100.0, d0=4.0, da=10.0, seed=1, rate=1e-2, ramp=1e-3,
     prog[top, 2] = pid
     scale[top, 2] = rate * edge
     v0 = np.zeros((N, 6))
-    dt, lam = stable_dt(g, mat, dt_fraction)
+    dt, lam = stable_dt(g, mat, dt_fraction, device=device)
     return finalize(g, mat, mode, prog, scale, P, v0, dt, f"tension_cube{edge:g}_s{seed}",
                     dict(d0=d0, da=da, seed=seed, rate=rate, lam_max=float(lam.max()),
                          height=edge, area=edge * edge, load_prog=pid, n_steps=n_steps))
@@ -824,7 +831,7 @@ def confined_compression_cube(edge=150.0, d0=4.0, da=12.0, seed=1, pressure=20.0
     N = x.shape[0]
     L = shape.size
     faces = _box_faces(x, L, 1e-9)
-    dt, lam = stable_dt(g, mat, dt_fraction)
+    dt, lam = stable_dt(g, mat, dt_fraction, device=device)
     t_end = n_steps * dt
     t_ramp = ramp_frac * t_end
     mode = np.zeros((N, 6), np.uint8)
@@ -894,7 +901,7 @@ def sliding_compression_cube(edge, d0=4.0, da=8.0, seed=0, rate=2.5e-2, ramp=1e-
     prog[top, 2] = pid
     scale[top, 2] = -rate * edge
     v0 = np.zeros((N, 6))
-    dts, lam = stable_dt(g, mat, dt_fraction)
+    dts, lam = stable_dt(g, mat, dt_fraction, device=device)
     return finalize(g, mat, mode, prog, scale, P, v0, dts if dt is None else dt,
                     f"sliding_cube{edge:g}_s{seed}",
                     dict(d0=d0, da=da, seed=seed, rate=rate, lam_max=float(lam.max()),
@@ -1079,7 +1086,7 @@ def cylinder_cycle(D=100.0, H=200.0, d0=2.0, da=4.0, seed=1, eps_t=1.2e-4, eps_c
     mode[cen, 5] = 1
     prog[top, 2] = pid
     scale[top, 2] = v
-    dt, lam = stable_dt(g, mat, dt_fraction)
+    dt, lam = stable_dt(g, mat, dt_fraction, device=device)
     return finalize(g, mat, mode, prog, scale, P, np.zeros((N, 6)), dt, f"cylinder{D:g}x{H:g}_s{seed}",
                     dict(d0=d0, da=da, seed=seed, lam_max=float(lam.max()), height=H,
                          area=np.pi * D * D / 4, load_prog=pid, total_time=float(t),
