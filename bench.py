@@ -482,9 +482,33 @@ def tess_case(sysd, reps=3):
     T = tets.shape[0]
     log(f"tessellation T={T}: host numpy {host_s:.3f} s, device (incl. transfers) {gpu_s * 1e3:.1f} ms, "
         f"max rel diff {diff:.2e}, ids equal {same_ids}")
-    return {"n_tets": int(T), "n_facets": int(12 * T), "n_particles": int(x.shape[0]), "host_numpy_s": host_s,
-            "device_s_incl_transfers": gpu_s, "speedup": host_s / gpu_s, "max_rel_diff_vs_host": diff,
-            "facet_ids_equal": same_ids}
+    rec = {"n_tets": int(T), "n_facets": int(12 * T), "n_particles": int(x.shape[0]), "host_numpy_s": host_s,
+           "device_s_incl_transfers": gpu_s, "speedup": host_s / gpu_s, "max_rel_diff_vs_host": diff,
+           "facet_ids_equal": same_ids}
+    # element bound of the stable step on the device geometry (per-tet mass
+    # shares from the cone records), against the host LAPACK bound when quick
+    c = g["tet_node_cones"]
+    tr = c[..., 4:7].sum(-1)
+    share = np.concatenate([np.repeat(S.RHO * c[..., :1], 3, -1), S.RHO * (tr[..., None] - c[..., 4:7])], -1)
+    geo = dict(g, x0=x, tet_nodes=tets, _elem_mass=share)
+    mat = S.MATERIAL_MB
+    ldpm.element_lambda_max(geo, mat["E0"], mat["alpha"], share)
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        lam = ldpm.element_lambda_max(geo, mat["E0"], mat["alpha"], share)
+        times.append(time.perf_counter() - t)
+    eb = {"device_s_incl_transfers": float(np.median(times))}
+    if T < 200000:
+        t = time.perf_counter()
+        lh = S.element_lambda_max(geo, mat["E0"], mat["alpha"])
+        eb["host_lapack_s"] = time.perf_counter() - t
+        eb["max_rel_diff_vs_host"] = float(np.abs(lam / lh - 1).max())
+    log(f"element bound T={T}: device {eb['device_s_incl_transfers'] * 1e3:.1f} ms"
+        + (f", host {eb['host_lapack_s']:.2f} s, max rel diff {eb['max_rel_diff_vs_host']:.2e}" if "host_lapack_s" in eb
+           else ""))
+    rec["element_bound"] = eb
+    return rec
 
 
 def cycle_run(sysd, precision, model=None, every=1000, launch=None):
