@@ -3,7 +3,7 @@ from FP64 runs of the solver, normalise, train the MLP on the GPU with the
 library's BF16 MFMA kernels, and install it into a mixed-precision system.
 
 The exact law stays both the fallback (facets leaving the envelope are
-handed back for good) and the judge of the surrogate's error.
+handed back for good) and the reference for the surrogate's error.
 """
 from __future__ import annotations
 
