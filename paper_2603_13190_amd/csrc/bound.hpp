@@ -10,7 +10,8 @@
 // and diagonalised by cyclic Jacobi rotations in round-robin order: in round
 // r the 24 indices form 12 disjoint pairs, (23, r) and ((r + k) mod 23,
 // (r - k) mod 23) for k = 1..11, so the 12 rotations of a round commute and
-// are applied together; 23 rounds make a sweep, in which every pair occurs
+// are applied together, block by 2 x 2 block of (row pair, column pair) in
+// one pass over the matrix; 23 rounds make a sweep, in which every pair occurs
 // once.  Sweeps stop when the off-diagonal part is below 1e-12 of the
 // matrix's Frobenius norm for all tetrahedra of the block; the diagonal then
 // holds the eigenvalues.
@@ -140,24 +141,22 @@ __global__ __launch_bounds__(256) void k_elem_lambda(ElemIn in, double* __restri
                 sCS[w][l][1] = s;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int e = l; e < 12 * EB_N; e += 64) {
-                const int k = e / EB_N, j = e % EB_N;
+            // A <- J^T A J, one 2 x 2 block (row pair k, column pair m) per
+            // item: the pairs partition the indices, so every entry belongs
+            // to one block; rows are rotated first, then columns
+            for (int e = l; e < 144; e += 64) {
+                const int k = e / 12, m = e % 12;
                 const int p = k == 0 ? 23 : (r + k) % 23, q = k == 0 ? r : (r - k + 23) % 23;
-                const double c = sCS[w][k][0], s = sCS[w][k][1];
-                const double ap = Am[p * EB_PITCH + j], aq = Am[q * EB_PITCH + j];
-                Am[p * EB_PITCH + j] = c * ap - s * aq;
-                Am[q * EB_PITCH + j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns: A <- A J
-            for (int e = l; e < 12 * EB_N; e += 64) {
-                const int k = e / EB_N, i = e % EB_N;
-                const int p = k == 0 ? 23 : (r + k) % 23, q = k == 0 ? r : (r - k + 23) % 23;
-                const double c = sCS[w][k][0], s = sCS[w][k][1];
-                const double ap = Am[i * EB_PITCH + p], aq = Am[i * EB_PITCH + q];
-                Am[i * EB_PITCH + p] = c * ap - s * aq;
-                Am[i * EB_PITCH + q] = s * ap + c * aq;
+                const int pp = m == 0 ? 23 : (r + m) % 23, qq = m == 0 ? r : (r - m + 23) % 23;
+                const double ck = sCS[w][k][0], sk = sCS[w][k][1], cm = sCS[w][m][0], sm = sCS[w][m][1];
+                const double b00 = Am[p * EB_PITCH + pp], b01 = Am[p * EB_PITCH + qq];
+                const double b10 = Am[q * EB_PITCH + pp], b11 = Am[q * EB_PITCH + qq];
+                const double x00 = ck * b00 - sk * b10, x01 = ck * b01 - sk * b11;
+                const double x10 = sk * b00 + ck * b10, x11 = sk * b01 + ck * b11;
+                Am[p * EB_PITCH + pp] = cm * x00 - sm * x01;
+                Am[p * EB_PITCH + qq] = sm * x00 + cm * x01;
+                Am[q * EB_PITCH + pp] = cm * x10 - sm * x11;
+                Am[q * EB_PITCH + qq] = sm * x10 + cm * x11;
             }
             __syncthreads();
         }
