@@ -467,7 +467,10 @@ ldpm_status ldpm_implicit_step(ldpm_system *s, const ldpm_implicit_opts *opts, i
  * mass = rho V, the inertia tensor J about the centre and the centroid
  * offset r.  All arrays are HOST memory owned by the caller; NULL outputs
  * are skipped.  Runs on `stream` (hipStream_t or NULL), allocates and frees
- * its device buffers, synchronises.                                        */
+ * its device buffers, synchronises.  Errors: LDPM_ERR_ARG (no tetrahedra,
+ * a node id out of range or repeated within a tetrahedron, a non-positive
+ * or non-finite diameter or density, non-finite centres; checked on the
+ * host before any device work), LDPM_ERR_ALLOC, LDPM_ERR_DEVICE.          */
 typedef struct {
     int64_t n_particles, n_tets;
     const double *x;           /* [3][N] centres */
