@@ -511,6 +511,29 @@ def tess_case(sysd, reps=3):
     return rec
 
 
+def generation_case(host_spec, args):
+    """The full-size cylinder generated again with the GPU paths
+    (tessellation, cell sums, mass shares and the element bound of the
+    stable step on the device; placement, Delaunay and the boundary
+    conditions on the host), against the host-built specimen (generated in a
+    worker process beside the other cases, so its time includes contention)."""
+    from paper_2603_13190_amd import specimen as S
+    d0 = args.cyl_full_d0
+    t = time.perf_counter()
+    g = S.cylinder_cycle(d0=d0, da=2 * d0, seed=1, device=True)
+    el = time.perf_counter() - t
+    diff = 0.0
+    for k in ("facet_cI", "facet_n", "facet_area", "facet_len", "mass", "inertia"):
+        a, b = np.asarray(g[k]), np.asarray(host_spec[k], np.float64)
+        diff = max(diff, float(np.abs(a - b).max() / np.abs(b).max()))
+    rec = {"generation_s_device_paths": el, "generation_s_host_worker": host_spec["meta"].get("generation_s"),
+           "dt_rel_diff": abs(g["dt"] - host_spec["dt"]) / host_spec["dt"], "max_rel_diff": diff,
+           "same_tets": bool(np.array_equal(g["tet_nodes"], host_spec["tet_nodes"]))}
+    log(f"cylinder generation with the GPU paths {el:.1f} s (host worker {rec['generation_s_host_worker']:.1f} s), "
+        f"dt rel diff {rec['dt_rel_diff']:.1e}, arrays {diff:.1e}, same tets {rec['same_tets']}")
+    return rec
+
+
 def cycle_run(sysd, precision, model=None, every=1000, launch=None):
     """Whole cyclic trajectory; nominal stress history, energy error, timing
     (reaction sampling outside the timed spans), surrogate share."""
@@ -891,6 +914,9 @@ def main():
             r = optional("tessellation_cylinder", lambda: tess_case(futs["cylinder"].result()))
             if r is not None:
                 out["tessellation"] = dict(out.get("tessellation", {}), cylinder_full=r)
+            r = optional("generation_cylinder", lambda: generation_case(futs["cylinder"].result(), args))
+            if r is not None:
+                out["tessellation"] = dict(out.get("tessellation", {}), cylinder_generation=r)
         pool.shutdown(cancel_futures=True)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----
