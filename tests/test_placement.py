@@ -2,8 +2,6 @@
 exactly the candidates its Python loop accepts: identical centres and
 diameters, bit for bit, on boxes and cylinders of several sizes and seeds.
 Input-generator code, no GPU."""
-import time
-
 import numpy as np
 import pytest
 
@@ -40,13 +38,3 @@ def test_native_placement_keeps_the_gap():
     np.fill_diagonal(dd, np.inf)
     assert np.all(dd >= lim)
 
-
-def test_native_placement_is_faster():
-    shape = S.Shape("cylinder", (40.0, 60.0))
-    t = time.perf_counter()
-    _place(shape, 2.0, 4.0, 3, native=False)
-    tp = time.perf_counter() - t
-    t = time.perf_counter()
-    _place(shape, 2.0, 4.0, 3, native=True)
-    tn = time.perf_counter() - t
-    assert tn < tp
