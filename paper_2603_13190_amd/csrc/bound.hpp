@@ -35,17 +35,14 @@ struct ElemIn {
     int64_t T;
 };
 
-// column d of G at one facet end: d < 3: sg * (-e_d); d >= 3: sg * (c x e_{d-3})
-__device__ __forceinline__ void eb_column(int d, double sg, const double c[3], double g[3])
+// column d of G at one facet end with offset c: d < 3: sg * (-e_d);
+// d >= 3: sg * (c x e_{d-3}), i.e. (0, c2, -c1), (-c2, 0, c0), (c1, -c0, 0);
+// written with selects so that no register array is indexed at run time
+__device__ __forceinline__ void eb_column(int d, double sg, double c0, double c1, double c2, double g[3])
 {
-    g[0] = g[1] = g[2] = 0.0;
-    if (d < 3) {
-        g[d] = -sg;
-    } else {
-        const int j = d - 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        g[j1] = sg * c[j2];   // (c x e_j)_{j+1} = c_{j+2}
-        g[j2] = -sg * c[j1];  // (c x e_j)_{j+2} = -c_{j+1}
-    }
+    g[0] = d == 0 ? -sg : (d == 4 ? -sg * c2 : (d == 5 ? sg * c1 : 0.0));
+    g[1] = d == 1 ? -sg : (d == 3 ? sg * c2 : (d == 5 ? -sg * c0 : 0.0));
+    g[2] = d == 2 ? -sg : (d == 3 ? -sg * c1 : (d == 4 ? sg * c0 : 0.0));
 }
 
 __global__ __launch_bounds__(256) void k_elem_lambda(ElemIn in, double* __restrict__ lam)
@@ -81,8 +78,8 @@ __global__ __launch_bounds__(256) void k_elem_lambda(ElemIn in, double* __restri
                 const int sr = r / 6, sc = c / 6;
                 double gr[3], gc[3];
                 // B_I = G(c^I); B_J = -G(c^J): the end's sign multiplies its column
-                eb_column(r % 6, sr ? -1.0 : 1.0, sr ? cj : ci, gr);
-                eb_column(c % 6, sc ? -1.0 : 1.0, sc ? cj : ci, gc);
+                eb_column(r % 6, sr ? -1.0 : 1.0, sr ? cj[0] : ci[0], sr ? cj[1] : ci[1], sr ? cj[2] : ci[2], gr);
+                eb_column(c % 6, sc ? -1.0 : 1.0, sc ? cj[0] : ci[0], sc ? cj[1] : ci[1], sc ? cj[2] : ci[2], gc);
                 const double gg = gr[0] * gc[0] + gr[1] * gc[1] + gr[2] * gc[2];
                 const double ngr = nn[0] * gr[0] + nn[1] * gr[1] + nn[2] * gr[2];
                 const double ngc = nn[0] * gc[0] + nn[1] * gc[1] + nn[2] * gc[2];
