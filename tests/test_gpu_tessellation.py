@@ -47,10 +47,13 @@ def test_small_specimens_match_the_oracle(case):
     g = ldpm.tessellate(x, d, t, S.RHO, cones=True)
     o = ora_tessellate(x, d, t, S.RHO)
     _compare(g, o)
-    # cone records: per-node sums give the oracle's mass and diagonal inertia
+    # cone records: each tetrahedron's share of its nodes' masses equals the
+    # oracle's, element by element, and the per-node sums its cell masses
     c = g["tet_node_cones"]
     tr = c[..., 4:7].sum(-1)
     share = np.concatenate([S.RHO * c[..., :1], S.RHO * (tr[..., None] - c[..., 4:7])], -1)   # (T,4,4)
+    ref = o["tet_node_share"][..., 2:]                                                         # rho V, diag J
+    assert np.abs(share - ref).max() <= TOL * np.abs(ref).max()
     N = x.shape[0]
     acc = np.zeros((N, 4))
     np.add.at(acc, np.asarray(t).ravel(), share.reshape(-1, 4))
