@@ -4,7 +4,16 @@ GPU training kernels' forward pass and gradients.
 
 Parameters: one flat vector, weights stored [out][in]:
 W1[64][9] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3].
-Loss: mean over samples of sum_j (y_j - target_j)^2.
+Loss: sum over samples of sum_j (y_j - target_j)^2, divided by `norm`
+(the number of samples unless given).
+
+Rounding points.  The surrogate runs its matrix products on BF16 operands
+with wider accumulation, so a value is rounded to BF16 wherever it becomes a
+matrix operand: the inputs x, the weights W (not the biases), the hidden
+activations h after tanh, the output gradient dL/dy and the pre-activation
+gradients dz.  `rnd` is the rounding applied at those points; with
+rnd=None every value stays FP64, which is the plain backpropagation the
+finite-difference pin checks.  bf16_points() gives the BF16 rounding.
 """
 import numpy as np
 
@@ -38,6 +47,16 @@ def bf16_round(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64).reshape(f.shape)
 
 
+def bf16_points(a):
+    """The rounding of matrix operands: FP64 -> FP32 -> BF16 (the GPU forms
+    each such value in FP32 before rounding it)."""
+    return bf16_round(a)
+
+
+def _ident(a):
+    return np.asarray(a, dtype=np.float64)
+
+
 def init_params(rng):
     """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases."""
     layers = []
@@ -47,35 +66,54 @@ def init_params(rng):
     return pack(layers)
 
 
-def forward(p, x):
-    L = unpack(p)
-    h = np.asarray(x, dtype=np.float64)
+def _layers(p, rnd):
+    return [(rnd(W), np.asarray(b, dtype=np.float64)) for W, b in unpack(p)]
+
+
+def _forward_all(L, x, rnd):
+    hs = [rnd(x)]
     for W, b in L[:-1]:
-        h = np.tanh(h @ W.T + b)
-    W, b = L[-1]
-    return h @ W.T + b
+        hs.append(rnd(np.tanh(hs[-1] @ W.T + b)))
+    W4, b4 = L[-1]
+    return hs, hs[-1] @ W4.T + b4
 
 
-def loss_and_grad(p, x, t):
-    """Mean squared-error loss and its gradient by backpropagation."""
-    L = unpack(p)
+def forward(p, x, rnd=None, magnitude=False):
+    """Network output y (n, 3); with magnitude=True also |h3| |W4|^T + |b4|,
+    the scale an output's rounding differences are measured against."""
+    rnd = rnd or _ident
+    L = _layers(p, rnd)
+    hs, y = _forward_all(L, np.asarray(x, dtype=np.float64), rnd)
+    if not magnitude:
+        return y
+    W4, b4 = L[-1]
+    return y, np.abs(hs[-1]) @ np.abs(W4).T + np.abs(b4)
+
+
+def loss_and_grad(p, x, t, rnd=None, norm=None, magnitude=False):
+    """Squared-error loss / norm and its gradient by backpropagation.
+
+    With magnitude=True a third value is returned: for every parameter the
+    sum of the absolute values of the terms its gradient adds up
+    (|dz|^T |h| for a weight, sum |dz| for a bias), the scale an entry's
+    rounding differences are measured against."""
+    rnd = rnd or _ident
+    L = _layers(p, rnd)
     x = np.asarray(x, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
     B = x.shape[0]
-    hs = [x]
-    for W, b in L[:-1]:
-        hs.append(np.tanh(hs[-1] @ W.T + b))
-    W4, b4 = L[-1]
-    y = hs[-1] @ W4.T + b4
+    norm = float(B if norm is None else norm)
+    hs, y = _forward_all(L, x, rnd)
     r = y - t
-    loss = np.sum(r * r) / B
-    dy = 2.0 * r / B
-    grads = [None] * 4
-    grads[3] = (dy.T @ hs[3], dy.sum(0))
-    dh = dy @ W4
-    for li in (2, 1, 0):
-        W, b = L[li]
-        dz = dh * (1.0 - hs[li + 1] ** 2)
+    loss = np.sum(r * r) / norm
+    dz = rnd(2.0 * r / norm)                       # dL/dy
+    grads, mags = [None] * 4, [None] * 4
+    for li in (3, 2, 1, 0):
+        W, _ = L[li]
         grads[li] = (dz.T @ hs[li], dz.sum(0))
-        dh = dz @ W
+        mags[li] = (np.abs(dz).T @ np.abs(hs[li]), np.abs(dz).sum(0))
+        if li > 0:
+            dz = rnd((dz @ W) * (1.0 - hs[li] ** 2))
+    if magnitude:
+        return loss, pack(grads), pack(mags)
     return loss, pack(grads)

@@ -475,6 +475,68 @@ def test_tension_reload_starts_at_e_tr():
     assert np.abs(t0 - np.minimum(p["E0"] * (again - elow), sbt)).max() < 1e-9 * p["sigma_t"]
 
 
+@pytest.mark.parametrize("kt", [0.0, 0.5])
+def test_reload_after_a_compression_excursion(kt):
+    """History across branch switches after an inelastic state (appendix,
+    fracturing and compressive behaviour; readings: the incremental base is
+    the stored traction and strain of the previous step whichever branch
+    produced them, and e_max changes in tension only).
+
+    Path, pure normal strain except for a shear excursion in compression:
+      1. tension to e_max = 3e-4, past the peak: t = sigma_bt(e_max);
+      2. unloading to e_a = 2e-5, below the zero-traction strain
+         e_z = e_max - sigma_bt/E0: t = 0 from e_z on (any k_t, since
+         e_tr <= e_z);
+      3. compression excursion e_N = -6e-4 sin(phi), e_M = 5e-4 sin(phi),
+         phi in (0, pi] (ending at zero strain), all elastic (far below sigma_c0 and the friction boundary):
+         incremental from the stored zero traction and strain e_a, so
+         t_N = E0 (e_N - e_a), t_M = alpha E0 e_M, and e_max stays 3e-4 even
+         though the effective strain of the excursion exceeds it;
+      4. tension again, e_N: 0 -> 2e-4 < e_max.  The stored traction
+         (-E0 e_a, 0, 0) enters as the previous effective traction E0 e_a and
+         the stored strain 0 as the previous effective strain, so
+         t = min(E0 (e + e_a), sigma_bt(e_max)) with the unchanged e_max; the
+         previous traction is positive, so k_t plays no part.
+    An e_max that moved in compression would lower the cap of step 4."""
+    p = dict(MB, k_t=kt)
+    E0, al = p["E0"], p["alpha"]
+    L = 6.0
+    emax, ea, c, g = 3e-4, 2e-5, 6e-4, 5e-4
+    Ht = 2 * E0 / (p["l_t"] / L - 1)
+    e0 = p["sigma_t"] / E0
+    sbt = p["sigma_t"] * math.exp(-Ht * (emax - e0) / p["sigma_t"])
+    assert ea < emax - sbt / E0                       # the unloading reaches zero traction
+    assert math.hypot(c, math.sqrt(al) * g) > emax     # the excursion's effective strain is larger
+    up = np.linspace(0, emax, 301)[1:]
+    down = np.linspace(emax, ea, 300)[1:]
+    ph = np.linspace(0, math.pi, 401)[1:]
+    exc = np.zeros((ph.size, 3))
+    exc[:, 0] = -c * np.sin(ph)
+    exc[:, 1] = g * np.sin(ph)
+    exc[-1] = 0.0                                     # ends at zero strain (compressive branch)
+    assert (exc[:, 0] <= 0).all()
+    again = np.linspace(0, 2e-4, 2001)[1:]
+    i2 = up.size + down.size
+    i3 = i2 + exc.shape[0]
+    path = np.zeros((i3 + again.size, 3))
+    path[:i2, 0] = np.concatenate([up, down])
+    path[i2:i3] = exc
+    path[i3:, 0] = again
+    T, EM = O.drive_facet(p, L, path)
+    assert T[i2 - 1, 0] == 0.0 and EM[i2 - 1] == emax
+    # 3: elastic compression and shear from the stored zero traction at e_a
+    assert np.abs(T[i2:i3, 0] - E0 * (exc[:, 0] - ea)).max() < 1e-12 * E0 * c
+    assert np.abs(T[i2:i3, 1] - al * E0 * exc[:, 1]).max() < 1e-12 * E0 * g
+    assert np.all(EM[i2:i3] == emax)
+    assert np.abs(T[i3 - 1] - [-E0 * ea, 0.0, 0.0]).max() < 1e-12 * E0 * c
+    # 4: reload capped by sigma_bt of the unchanged e_max
+    expect = np.minimum(E0 * (again + ea), sbt)
+    assert (E0 * (again + ea) < sbt).any() and (E0 * (again + ea) > sbt).any()
+    assert np.abs(T[i3:, 0] - expect).max() < 1e-12 * p["sigma_t"]
+    assert np.all(T[i3:, 1:] == 0.0)
+    assert np.all(EM[i3:] == emax)
+
+
 def test_branch_switches_are_continuous_for_elastic_states():
     """Reading of the branch switch (history rebuilt from the stored vectors,
     whichever branch produced them): on an elastic path that crosses e_N = 0
