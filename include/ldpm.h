@@ -187,7 +187,8 @@ ldpm_status ldpm_step(ldpm_system *s, int64_t n_steps);
 
 /* Like ldpm_step, but brackets every facet-kernel and particle-kernel launch
  * with HIP events on the handle's stream, waits after each step, and returns
- * the summed kernel times in milliseconds (for roofline measurements). */
+ * the summed kernel times in milliseconds (for roofline measurements).
+ * LDPM_ERR_STATE on a handle that integrates implicitly.                   */
 ldpm_status ldpm_step_profiled(ldpm_system *s, int64_t n_steps, double *facet_ms,
                                double *particle_ms);
 
@@ -241,7 +242,10 @@ ldpm_status ldpm_get_launch(ldpm_system *s, ldpm_launch *out);
  * temporary device buffer of the state's size is allocated), so the
  * trajectory is unchanged.  Choices are cached for the process per (GPU
  * architecture, system shape); a cache hit returns with *n_trials = 0.
- * trials (may be NULL) receives up to max_trials timings.                   */
+ * trials (may be NULL) receives up to max_trials timings.
+ * LDPM_ERR_STATE while a surrogate is installed or a sample capture is
+ * active (their hand-back flags and rows are not part of the saved state:
+ * tune first) and on a handle that integrates implicitly.                  */
 typedef struct {
     ldpm_launch launch;
     double us_per_step;

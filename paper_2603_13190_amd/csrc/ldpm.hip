@@ -825,6 +825,7 @@ ldpm_status ldpm_step_profiled(ldpm_system* s, int64_t n_steps, double* facet_ms
 {
     if (!s || !facet_ms || !particle_ms) return fail(LDPM_ERR_ARG, "null argument");
     if (n_steps < 0) return fail(LDPM_ERR_ARG, "negative step count");
+    if (s->imp_on) return fail(LDPM_ERR_STATE, "the handle integrates implicitly (ldpm_implicit_step)");
     constexpr int CH = 128;  // steps per chunk of events
     std::vector<hipEvent_t> ev(4 * CH);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
@@ -1044,6 +1045,12 @@ ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* 
 {
     if (!s) return fail(LDPM_ERR_ARG, "null handle");
     if (steps_per_trial <= 0) return fail(LDPM_ERR_ARG, "steps_per_trial must be positive");
+    // the trial steps restore only the plain step's state: the surrogate's
+    // sticky hand-back flags and a capture's rows would keep the trials'
+    // traces, so tuning is refused while either is active
+    if (s->sg_on) return fail(LDPM_ERR_STATE, "autotune: a surrogate is installed (tune before ldpm_set_surrogate)");
+    if (s->cp_on) return fail(LDPM_ERR_STATE, "autotune: a sample capture is active");
+    if (s->imp_on) return fail(LDPM_ERR_STATE, "autotune: the handle integrates implicitly");
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, s->device));
     TuneKey key{prop.gcnArchName, s->N, s->T, s->F, s->E, s->nspec, s->prec, s->law, s->mblk ? 1 : 0};

@@ -57,3 +57,8 @@ def batch_full():
 
 def cylinder_full():
     return cached("cylinder_full", lambda: S.cylinder_cycle(d0=2.0, da=4.0, seed=1))
+
+
+def cylinder_bench():
+    """The benchmark's cylinder: 100 x 200 mm, d 1.1-2.2 mm (12.66M facets)."""
+    return cached("cylinder_bench", lambda: S.cylinder_cycle(d0=1.1, da=2.2, seed=1))

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_util import (batch_full, confined_full, cylinder_full, elastic_full, rel)
+from tests.gpu_util import (batch_full, confined_full, cylinder_bench, cylinder_full, elastic_full, rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -85,3 +85,77 @@ def test_cylinder_sampled():
     st = g.read_state()
     for f in ("q", "v", "t"):
         assert rel(st[f], getattr(o, f)) <= 1e-9, f
+
+
+def _cylinder_loaded_state(s):
+    """A seeded state around the tensile peak of the benchmark's cylinder:
+    axial strain 1.0e-4 (the tensile strength is reached near 9e-5), facet
+    tractions up to 4 MPa in tension and 20 MPa in compression, e_max up to
+    2e-4 (softening facets)."""
+    from paper_2603_13190_amd import specimen as S
+    return S.synthetic_state(s, seed=11, strain=np.diag([-2e-5, -2e-5, 1.0e-4]), t_normal=(-20.0, 4.0),
+                             t_shear=3.0, emax_max=2e-4, step=6000)
+
+
+def _oracle_from(s, st):
+    o = O.Oracle(s)
+    e_old = o.strains(st["q"] - s["dt"] * st["v"])     # q^{n-1} = q^n - dt v^{n-1/2}
+    o.set_state(st["q"], st["v"], st["t"], e_old, st["emax"], st["fext"], st["step"])
+    return o
+
+
+@pytest.mark.timeout(900)
+def test_cylinder_bench_one_step_and_trajectory_from_a_loaded_state():
+    """The benchmark's 12.66M-facet cylinder (d 1.1-2.2 mm) in the benchmark's
+    launch shape: one step from a seeded loaded state (tension past the peak,
+    compression, friction, softening histories), then 20 more steps, FP64 on
+    both sides."""
+    s = cylinder_bench()
+    assert s["meta"]["F"] > 12_000_000
+    st = _cylinder_loaded_state(s)
+    o = _oracle_from(s, st)
+    g = gpu(s, init_state=st)
+    o.step(1)
+    g.step(1)
+    sig_t = s["material"]["sigma_t"]
+    assert (o.t[:, 0] > 0.5 * sig_t).sum() > 100000              # tensile facets near the strength
+    assert (o.emax > o.e[:, 0]).sum() > 100000                     # unloading / softened histories
+    st1 = g.read_state()
+    for f in ("q", "v", "t", "emax", "fext"):
+        assert rel(st1[f], getattr(o, f)) <= 1e-10, f
+    o.step(20)
+    g.step(20)
+    st2 = g.read_state()
+    for f in ("q", "v", "t", "emax", "fext"):
+        assert rel(st2[f], getattr(o, f)) <= 1e-9, f
+    prog = s["meta"]["load_prog"]
+    assert abs(g.reaction(prog) - o.reaction_sum(prog)) <= 1e-9 * abs(o.reaction_sum(prog))
+
+
+@pytest.mark.timeout(900)
+def test_cylinder_bench_mixed_precision_short_trajectory():
+    """The same loaded state, 20 steps in mixed precision (FP32 facets, FP64
+    state) against the FP64 oracle: the top-face reaction within 1e-4 (the
+    mixed form's stated bar over a whole trajectory is 1 % of the peak
+    stress), positions within 1e-6, and the facet tractions within 1e-4 of
+    the largest traction except on at most one facet in a million: a facet
+    whose normal strain sits within FP32 rounding of zero may take the other
+    branch of the law than in FP64, which is a different but equally valid
+    evaluation of the same law."""
+    s = cylinder_bench()
+    st = _cylinder_loaded_state(s)
+    o = _oracle_from(s, st)
+    g = gpu(s, init_state=st, precision="mixed")
+    o.step(20)
+    g.step(20)
+    st2 = g.read_state()
+    scale = np.abs(o.t).max()
+    err = np.abs(st2["t"] - o.t).max(1) / scale
+    prog = s["meta"]["load_prog"]
+    err_r = abs(g.reaction(prog) - o.reaction_sum(prog)) / abs(o.reaction_sum(prog))
+    nbad = int((err > 1e-4).sum())
+    print("cylinder mixed vs oracle after 20 steps: traction (99.9999 %)", np.quantile(err, 0.999999),
+          "max", err.max(), "facets above 1e-4:", nbad, "reaction", err_r, "q", rel(st2["q"], o.q))
+    assert nbad <= 1e-6 * s["meta"]["F"]
+    assert err_r <= 1e-4
+    assert rel(st2["q"], o.q) <= 1e-6

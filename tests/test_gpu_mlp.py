@@ -1,11 +1,22 @@
 """GPU training kernels of the surrogate MLP (BF16 MFMA, FP32 accumulate)
-against the FP64 reference with the same BF16-rounded parameters/inputs."""
+against the FP64 reference that rounds to BF16 at the same points (inputs,
+weights, activations, dL/dy, dz), entry by entry.
+
+Per-entry tolerance: both sides round at the same points, so they differ by
+the FP32 accumulation order, the tanh evaluation (~1e-7) and the occasional
+BF16 rounding that these push across a rounding boundary (one BF16 ulp,
+2^-8 to 2^-7 of the value, in one term and whatever it feeds).  An entry is
+held to 2^-6 of the sum of the absolute values of the terms it adds up, the
+magnitude the reference returns with it, plus 1e-6 of the largest entry."""
 import numpy as np
 import pytest
 
 import oracle.mlp_ref as M
 
 pytestmark = pytest.mark.gpu
+
+REL = 2.0 ** -6
+FLOOR = 1e-6
 
 
 def trainer(p):
@@ -21,14 +32,21 @@ def _data(n, seed):
     return x, y
 
 
+def _entrywise(got, ref, mag, what):
+    lim = REL * mag + FLOOR * np.abs(ref).max()
+    ratio = np.abs(got - ref) / lim
+    print(f"{what}: worst |gpu - ref| / tolerance = {ratio.max():.3e}, "
+          f"worst |gpu - ref| / magnitude = {(np.abs(got - ref) / np.maximum(mag, 1e-30)).max():.3e}")
+    assert ratio.max() <= 1.0, (what, int(np.argmax(ratio)))
+
+
 def test_forward_matches_reference():
     rng = np.random.default_rng(3)
     p = M.init_params(rng).astype(np.float32)
     x, _ = _data(1000, 4)
     g = trainer(p).forward(x)
-    ref = M.forward(M.bf16_round(p), M.bf16_round(x))
-    err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
-    assert err < 2e-2, err
+    ref, mag = M.forward(p.astype(np.float64), x.astype(np.float64), rnd=M.bf16_points, magnitude=True)
+    _entrywise(g, ref, mag, "forward")
 
 
 def test_gradient_matches_reference():
@@ -38,21 +56,35 @@ def test_gradient_matches_reference():
     tr = trainer(p)
     tr.set_data(x, y)
     loss, g = tr.grad(256, 0)
-    lref, gref = M.loss_and_grad(M.bf16_round(p), M.bf16_round(x), y.astype(np.float64))
-    assert abs(loss - lref) < 2e-2 * lref
-    err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
-    assert err < 3e-2, err
-    # every layer, not only the largest one
+    lref, gref, mag = M.loss_and_grad(p.astype(np.float64), x.astype(np.float64), y.astype(np.float64),
+                                      rnd=M.bf16_points, norm=256, magnitude=True)
+    assert abs(loss - lref) <= 1e-5 * lref
     k = 0
-    for o, i in M.SIZES:
-        for n in (o * i, o):
+    for li, (o, i) in enumerate(M.SIZES):
+        for n, name in ((o * i, "W"), (o, "b")):
             seg = slice(k, k + n)
-            e = np.linalg.norm(g[seg] - gref[seg]) / max(np.linalg.norm(gref[seg]), 1e-12)
-            assert e < 6e-2, (o, i, n, e)
+            _entrywise(g[seg].astype(np.float64), gref[seg], mag[seg], f"{name}{li + 1}")
             k += n
     # bitwise reproducible (fixed-order reduction over blocks)
     loss2, g2 = tr.grad(256, 0)
     assert np.array_equal(g, g2) and loss == loss2
+
+
+def test_gradient_over_several_blocks_and_a_wrapped_batch():
+    """A batch of 1024 rows from offset 900 of 1500 (16 blocks, wrapping
+    around the data set), entry by entry."""
+    rng = np.random.default_rng(9)
+    p = M.init_params(rng).astype(np.float32)
+    x, y = _data(1500, 10)
+    tr = trainer(p)
+    tr.set_data(x, y)
+    loss, g = tr.grad(1024, 900)
+    idx = (900 + np.arange(1024)) % 1500
+    lref, gref, mag = M.loss_and_grad(p.astype(np.float64), x[idx].astype(np.float64),
+                                      y[idx].astype(np.float64), rnd=M.bf16_points, norm=1024,
+                                      magnitude=True)
+    assert abs(loss - lref) <= 1e-5 * lref
+    _entrywise(g.astype(np.float64), gref, mag, "all parameters")
 
 
 def test_training_reduces_loss():
@@ -68,5 +100,5 @@ def test_training_reduces_loss():
     # trained parameters evaluated by the reference agree with the GPU forward
     pt = tr.params()
     yg = tr.forward(x[:2000])
-    yr = M.forward(M.bf16_round(pt), M.bf16_round(x[:2000]))
-    assert np.linalg.norm(yg - yr) / np.linalg.norm(yr) < 2e-2
+    yr, mag = M.forward(pt.astype(np.float64), x[:2000].astype(np.float64), rnd=M.bf16_points, magnitude=True)
+    _entrywise(yg, yr, mag, "trained forward")

@@ -10,6 +10,7 @@ import pytest
 
 import oracle as O
 from paper_2603_13190_amd import specimen as S
+from tests.conftest import cached
 from tests.gpu_util import (confined_small, elastic_small, oracle_state, rel, tension_full,
                             tension_small)
 
@@ -279,6 +280,59 @@ def test_persistent_launch_is_bitwise_equal(tb):
     g.sync()
     for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
         assert np.array_equal(st[k], ref[k]), k
+
+
+def _uneven3():
+    specs = [S.sliding_compression_cube(e, d0=4.0, da=8.0, seed=20 + i, rate=1.0, ramp=2e-4)
+             for i, e in enumerate((20.0, 31.0, 25.0))]
+    return S.concat_specimens(specs, dt=min(x["dt"] for x in specs))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("tb", [8, 16, 32, 64])
+def test_persistent_launch_uneven_batch_is_bitwise_equal(precision, tb):
+    """Three specimens of uneven size batched into one system: persistent
+    cooperative launches (a chunk boundary at 1024 steps) give the same bits
+    as two kernels per step, in FP64 and in mixed precision."""
+    batch = cached("uneven3_seed20", _uneven3)
+    r = gpu(batch, precision=precision)
+    r.set_launch(tets_per_block=16, persistent=0)
+    ref = r.step(1100).read_state()
+    g = gpu(batch, precision=precision)
+    g.set_launch(tets_per_block=tb, persistent=1)
+    st = g.step(1100).read_state()
+    g.sync()
+    assert np.abs(st["t"]).max() > 0
+    for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
+        assert np.array_equal(st[k], ref[k]), k
+    for i in range(3):
+        assert g.energy(i) == r.energy(i), i
+
+
+def test_autotune_is_refused_with_a_surrogate_or_a_capture():
+    """Trial steps would leave their traces in the surrogate's hand-back
+    flags and in a capture's rows: tuning is refused while either is active,
+    and the trajectory is untouched."""
+    from paper_2603_13190_amd import surrogate as SG
+    from paper_2603_13190_amd.ldpm import LDPM_ERR_STATE, LdpmError
+    s = tension_small()
+    g = gpu(s, precision="mixed")
+    g.set_surrogate(SG.init_params(0), np.zeros(9), np.ones(9), np.ones(3), np.full(9, -1.0),
+                    np.full(9, 1.0), 0.8, 0.9, 0.05)
+    g.step(10)
+    with pytest.raises(LdpmError) as ei:
+        g.autotune(steps_per_trial=5)
+    assert ei.value.status == LDPM_ERR_STATE
+    assert g.read_state()["step"] == 10
+    c = gpu(s, precision="fp64")
+    c.capture_begin(1000, facet_stride=50, facet_offset=0, step_stride=5, kappa_t=0.8, kappa_c=0.9,
+                    damage_max=0.05)
+    c.step(10)
+    with pytest.raises(LdpmError) as ei:
+        c.autotune(steps_per_trial=5)
+    assert ei.value.status == LDPM_ERR_STATE
+    rows = c.capture_end()
+    assert set(np.unique(rows["step"])) <= {0, 5}
 
 
 def test_autotune_keeps_the_trajectory():

@@ -119,12 +119,16 @@ def test_surrogate_end_to_end_accuracy_and_sticky_gate():
         counts.append(g.surrogate_count())
     so, sg = np.array(so), np.array(sg)
     F = ts["meta"]["F"]
+    hist_err = np.abs(sg - so).max() / abs(so.max())
     print("handed back:", counts, "of", F, "peak err", abs(sg.max() - so.max()) / abs(so.max()),
-          "holdout rmse", model.holdout_rmse)
+          "history err", hist_err, "energy err", g.energy()["err"], "holdout rmse", model.holdout_rmse)
     assert all(b >= a for a, b in zip(counts, counts[1:]))
     assert counts[0] < F                         # the surrogate does carry facets
-    assert abs(sg.max() - so.max()) <= 0.03 * abs(so.max())
-    assert g.energy()["err"] <= 1e-2
+    # the surrogate form's bar: peak stress within 1 %, energy balance within
+    # 1e-3; every sample of the nominal stress history within 1 % of the peak
+    assert abs(sg.max() - so.max()) <= 1e-2 * abs(so.max())
+    assert hist_err <= 1e-2
+    assert g.energy()["err"] <= 1e-3
 
 
 def test_surrogate_arguments_are_validated():
