@@ -4,12 +4,13 @@ TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 CPU-baseline leg of the benchmark, never by the solver package.
 
 Parity unpinned (no external reference exists for these; they follow the
-documented readings, and the GPU path is compared against them): the
-tessellation details, the history reset at branch switches, the e_max rule,
-whole trajectories of the inelastic workloads, and the reading that the
-facet law takes a random perturbation's jump as an increment of its own
-(its invariants are pinned: masking, rigid jumps, elastic work, consistency
-of history and positions, energy balance).
+documented readings, and the GPU path is compared against them): whole
+trajectories of the inelastic workloads, and the reading that the facet law
+takes a random perturbation's jump as an increment of its own (its
+invariants are pinned: masking, rigid jumps, elastic work, consistency of
+history and positions, energy balance).  The history across branch switches
+and the e_max rule are pinned by closed forms along a tension - unloading -
+compression - reloading path.
 """
 from __future__ import annotations
 
@@ -51,6 +52,17 @@ class OraState(C.Structure):
     _fields_ = [("q", _dp), ("v", _dp), ("t", _dp), ("e", _dp), ("emax", _dp), ("fext", _dp),
                 ("W_int", C.c_double), ("W_ext", C.c_double), ("W_kin", C.c_double),
                 ("W_kin0", C.c_double), ("W_pert", C.c_double), ("step", C.c_int64)]
+
+
+def use_library(path):
+    """Load the oracle from another build of the same source (e.g. one
+    optimised for the host, oracle.build.build_native) instead of the
+    in-tree library; only before the library is first used."""
+    global _LIB_PATH
+    if _lib is not None and os.path.abspath(path) != os.path.abspath(_LIB_PATH):
+        raise RuntimeError("the oracle library is already loaded")
+    _LIB_PATH = path
+    return lib()
 
 
 def lib():

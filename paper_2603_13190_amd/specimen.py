@@ -1068,12 +1068,14 @@ def cylinder_cycle(D=100.0, H=200.0, d0=2.0, da=4.0, seed=1, eps_t=1.2e-4, eps_c
         legs += [eps_t * H, -eps_c * H]
     t_pts, v_pts = [0.0], [v]
     u, t = 0.0, 0.0
+    leg_end = []
     for target in legs:
         dur = abs(target - u) / v
         sgn = 1.0 if target > u else -1.0
         t_pts += [t + 1e-12, t + dur]
         v_pts += [sgn * v, sgn * v]
         t, u = t + dur, target
+        leg_end.append(t)
     t_pts = np.array(t_pts[1:])
     v_pts = np.array(v_pts[1:])
     pid = P.add(np.concatenate([[0.0], t_pts, [t + 1e-9, 1e9]]),
@@ -1090,7 +1092,8 @@ def cylinder_cycle(D=100.0, H=200.0, d0=2.0, da=4.0, seed=1, eps_t=1.2e-4, eps_c
     return finalize(g, mat, mode, prog, scale, P, np.zeros((N, 6)), dt, f"cylinder{D:g}x{H:g}_s{seed}",
                     dict(d0=d0, da=da, seed=seed, lam_max=float(lam.max()), height=H,
                          area=np.pi * D * D / 4, load_prog=pid, total_time=float(t),
-                         n_steps=int(np.ceil(t / dt))))
+                         n_steps=int(np.ceil(t / dt)), eps_t=eps_t, eps_c=eps_c, rate=rate,
+                         leg_end_steps=[int(np.ceil(te / dt)) for te in leg_end]))
 
 
 def perturbation(n_particles, eta, seed, index):

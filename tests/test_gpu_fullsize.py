@@ -133,29 +133,42 @@ def test_cylinder_bench_one_step_and_trajectory_from_a_loaded_state():
 
 
 @pytest.mark.timeout(900)
-def test_cylinder_bench_mixed_precision_short_trajectory():
-    """The same loaded state, 20 steps in mixed precision (FP32 facets, FP64
-    state) against the FP64 oracle: the top-face reaction within 1e-4 (the
-    mixed form's stated bar over a whole trajectory is 1 % of the peak
-    stress), positions within 1e-6, and the facet tractions within 1e-4 of
-    the largest traction except on at most one facet in a million: a facet
-    whose normal strain sits within FP32 rounding of zero may take the other
-    branch of the law than in FP64, which is a different but equally valid
-    evaluation of the same law."""
+def test_cylinder_bench_mixed_precision_from_a_loaded_state():
+    """The same loaded state in mixed precision (FP32 facets, FP64 state)
+    against the FP64 oracle.
+
+    One step, facet by facet: tractions within 1e-5 of the largest traction,
+    except where FP32 and FP64 take different branches of the law, which
+    they may only for a normal strain within FP32 rounding of zero (the law
+    is discontinuous there: at most one facet in a million); velocities and
+    positions within 1e-6 at every particle no such facet touches.  Then 20
+    steps: the top-face reaction within 1e-4 (the mixed form's stated bar
+    over a whole trajectory is 1 % of the peak stress).  Facet by facet, a
+    random loaded state is not comparable over several steps: a flipped
+    facet's force jump moves its particles, and the difference spreads by one
+    particle layer per step."""
     s = cylinder_bench()
     st = _cylinder_loaded_state(s)
     o = _oracle_from(s, st)
     g = gpu(s, init_state=st, precision="mixed")
-    o.step(20)
-    g.step(20)
-    st2 = g.read_state()
+    o.step(1)
+    g.step(1)
+    st1 = g.read_state()
     scale = np.abs(o.t).max()
-    err = np.abs(st2["t"] - o.t).max(1) / scale
+    err = np.abs(st1["t"] - o.t).max(1) / scale
+    bad = np.nonzero(err > 1e-5)[0]
+    print("cylinder mixed vs oracle, one step: traction 99.9999 %", np.quantile(err, 0.999999), "max",
+          err.max(), "facets above 1e-5:", bad.size, "their |e_N|:", np.abs(o.e[bad, 0]).max() if bad.size else 0)
+    assert bad.size <= 1e-6 * s["meta"]["F"]
+    assert np.all(np.abs(o.e[bad, 0]) <= 1e-9)          # branch decisions at e_N ~ 0 only
+    keep = np.ones(s["meta"]["N"], bool)
+    keep[s["facet_I"][bad]] = False
+    keep[s["facet_J"][bad]] = False
+    for f in ("q", "v"):
+        assert rel(st1[f][keep], getattr(o, f)[keep]) <= 1e-6, f
+    o.step(19)
+    g.step(19)
     prog = s["meta"]["load_prog"]
     err_r = abs(g.reaction(prog) - o.reaction_sum(prog)) / abs(o.reaction_sum(prog))
-    nbad = int((err > 1e-4).sum())
-    print("cylinder mixed vs oracle after 20 steps: traction (99.9999 %)", np.quantile(err, 0.999999),
-          "max", err.max(), "facets above 1e-4:", nbad, "reaction", err_r, "q", rel(st2["q"], o.q))
-    assert nbad <= 1e-6 * s["meta"]["F"]
+    print("reaction after 20 steps", err_r)
     assert err_r <= 1e-4
-    assert rel(st2["q"], o.q) <= 1e-6
