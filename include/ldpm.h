@@ -382,6 +382,23 @@ typedef struct {
 ldpm_status ldpm_compare_fields(const double *x, const double *ref, int64_t n, double cap, void *stream,
                                 ldpm_field_stats *out);
 
+/* Allocation-free variant of ldpm_compare_fields, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, validation,
+ * results (bitwise) and errors as ldpm_compare_fields; it calls no hipMalloc,
+ * hipFree or other allocating routine.  Its block partials and results live
+ * in a file-scope device array of the library (2048 partials of 64 bytes
+ * plus the results, about 128 KiB), one per GPU, held until the process
+ * ends; the first call on a device resolves that array's address there.
+ * The scratch need does not grow with n (the grid is capped at 2048
+ * blocks), so no n is refused for size.  Every call on a GPU uses the same
+ * array: calls that overlap on one GPU (several host threads or streams at
+ * once) race on it, and the caller must serialise them.  Each call writes
+ * every partial it reads, so nothing is carried from the previous call.
+ * Synchronises `stream` before returning.                                  */
+ldpm_status ldpm_compare_fields_noalloc(const double *x, const double *ref, int64_t n, double cap,
+                                        void *stream, ldpm_field_stats *out);
+
 /* ---- Random perturbation of the solution ---------------------------------
  * The paper tests the stability of a strain-softening response by adding,
  * at regular intervals, a random vector uniform in [-eta/2, eta/2] to all

@@ -1310,28 +1310,57 @@ ldpm_status ldpm_volumetric_strain(ldpm_system* s, double* ev)
     return LDPM_OK;
 }
 
-ldpm_status ldpm_compare_fields(const double* x, const double* ref, int64_t n, double cap, void* stream,
-                                ldpm_field_stats* out)
+}  // extern "C"
+
+// Buffer of the field comparison: CMP_MAX_BLOCKS block partials, then the
+// 7 results (and one spare double).
+constexpr size_t CMP_BUF_BYTES = (size_t)CMP_MAX_BLOCKS * sizeof(Moments) + 8 * sizeof(double);
+
+// The allocation-free entry point's copy of that buffer: one per GPU, held by
+// the process.  On the host `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress (cmp_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[CMP_BUF_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mtx;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// device address of `scratch` on GPU dev (the current device), resolved on
+// the first call per device and kept
+ldpm_status cmp_scratch_ptr(int dev, void** out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return fail(LDPM_ERR_DEVICE, "compare_fields_noalloc: device %d beyond the %d supported", dev,
+                    SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LDPM_ERR_DEVICE, "compare_fields_noalloc: hipGetSymbolAddress failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LDPM_OK;
+}
+
+ldpm_status cmp_check(const double* x, const double* ref, int64_t n, ldpm_field_stats* out, int* dev)
 {
     if (!x || !ref || !out) return fail(LDPM_ERR_ARG, "null argument");
     if (n <= 0) return fail(LDPM_ERR_ARG, "compare_fields: n must be positive");
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    if (!on_device(x, dev) || !on_device(ref, dev))
+    HIP_TRY(hipGetDevice(dev));
+    if (!on_device(x, *dev) || !on_device(ref, *dev))
         return fail(LDPM_ERR_ARG, "compare_fields: x and ref must be device memory of the current GPU");
-    hipStream_t st = (hipStream_t)stream;
+    return LDPM_OK;
+}
+
+// the comparison proper, on a buffer of CMP_BUF_BYTES device bytes
+ldpm_status cmp_run(const double* x, const double* ref, int64_t n, double cap, hipStream_t st, void* mem,
+                    ldpm_field_stats* out)
+{
     const int G = (int)std::min<int64_t>(CMP_MAX_BLOCKS, (n + CMP_THREADS - 1) / CMP_THREADS);
-    // one buffer per device (partials and result), kept for the process;
-    // calls are serialised (each waits for its stream before returning)
-    static std::mutex mtx;
-    static std::unordered_map<int, void*> bufs;
-    std::lock_guard<std::mutex> lock(mtx);
-    void*& mem = bufs[dev];
-    const size_t bytes = (size_t)CMP_MAX_BLOCKS * sizeof(Moments) + 8 * sizeof(double);
-    if (!mem && hipMalloc(&mem, bytes) != hipSuccess) {
-        mem = nullptr;
-        return fail(LDPM_ERR_ALLOC, "compare_fields: hipMalloc(%zu) failed", bytes);
-    }
     Moments* part = (Moments*)mem;
     double* res = (double*)((char*)mem + (size_t)CMP_MAX_BLOCKS * sizeof(Moments));
     const int use_cap = (cap > 0.0 && std::isfinite(cap)) ? 1 : 0;
@@ -1350,6 +1379,43 @@ ldpm_status ldpm_compare_fields(const double* x, const double* ref, int64_t n, d
     out->ref_max = r[5];
     out->nrmse = r[6];
     return LDPM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ldpm_status ldpm_compare_fields(const double* x, const double* ref, int64_t n, double cap, void* stream,
+                                ldpm_field_stats* out)
+{
+    int dev = 0;
+    ldpm_status stc = cmp_check(x, ref, n, out, &dev);
+    if (stc != LDPM_OK) return stc;
+    // one buffer per device (partials and result), kept for the process;
+    // calls are serialised (each waits for its stream before returning)
+    static std::mutex mtx;
+    static std::unordered_map<int, void*> bufs;
+    std::lock_guard<std::mutex> lock(mtx);
+    void*& mem = bufs[dev];
+    if (!mem && hipMalloc(&mem, CMP_BUF_BYTES) != hipSuccess) {
+        mem = nullptr;
+        return fail(LDPM_ERR_ALLOC, "compare_fields: hipMalloc(%zu) failed", CMP_BUF_BYTES);
+    }
+    return cmp_run(x, ref, n, cap, (hipStream_t)stream, mem, out);
+}
+
+ldpm_status ldpm_compare_fields_noalloc(const double* x, const double* ref, int64_t n, double cap, void* stream,
+                                        ldpm_field_stats* out)
+{
+    int dev = 0;
+    ldpm_status stc = cmp_check(x, ref, n, out, &dev);
+    if (stc != LDPM_OK) return stc;
+    // the partials of any n fit: the grid is capped at CMP_MAX_BLOCKS blocks
+    static_assert((size_t)CMP_MAX_BLOCKS * sizeof(Moments) + 7 * sizeof(double) <= sizeof(scratch),
+                  "comparison scratch");
+    void* mem = nullptr;
+    stc = cmp_scratch_ptr(dev, &mem);
+    if (stc != LDPM_OK) return stc;
+    return cmp_run(x, ref, n, cap, (hipStream_t)stream, mem, out);
 }
 
 extern "C++" template <typename R, int LAW>

@@ -27,6 +27,7 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
            "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_capture_begin",
            "ldpm_capture_end", "ldpm_crack_opening", "ldpm_volumetric_strain", "ldpm_compare_fields",
+           "ldpm_compare_fields_noalloc",
            "ldpm_perturb", "ldpm_implicit_step", "ldpm_tessellate", "ldpm_element_lambda",
            "ldpm_last_error")
 
@@ -173,6 +174,7 @@ def lib():
         L.ldpm_volumetric_strain.argtypes = [C.c_void_p, C.c_void_p]
         L.ldpm_compare_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
                                           C.POINTER(FieldStats)]
+        L.ldpm_compare_fields_noalloc.argtypes = L.ldpm_compare_fields.argtypes
         L.ldpm_perturb.argtypes = [C.c_void_p, _dp, _dp]
         L.ldpm_implicit_step.argtypes = [C.c_void_p, C.POINTER(ImplicitOpts), C.c_int64,
                                          C.POINTER(ImplicitStats)]
@@ -546,10 +548,12 @@ def _check_out(t, shape):
         raise ValueError(f"output must be a contiguous float64 device tensor of shape {shape}")
 
 
-def compare_fields(x, ref, cap=None, stream=None):
+def compare_fields(x, ref, cap=None, stream=None, noalloc=False):
     """Pearson's correlation and NRMSE (percent, normalised by max ref) of
     two device tensors of the same size (float64), optionally limited to cap
-    first.  Returns a dict."""
+    first.  Returns a dict.  noalloc: ldpm_compare_fields_noalloc (its
+    partials in the library's static device buffer) instead of
+    ldpm_compare_fields."""
     import torch
     for t in (x, ref):
         if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
@@ -558,9 +562,10 @@ def compare_fields(x, ref, cap=None, stream=None):
         raise ValueError("fields must have the same size")
     st = torch.cuda.current_stream() if stream is None else stream
     o = FieldStats()
-    _check(lib().ldpm_compare_fields(C.c_void_p(x.data_ptr()), C.c_void_p(ref.data_ptr()), int(x.numel()),
-                                     float(cap) if cap is not None else 0.0, C.c_void_p(st.cuda_stream),
-                                     C.byref(o)))
+    L = lib()
+    fn = L.ldpm_compare_fields_noalloc if noalloc else L.ldpm_compare_fields
+    _check(fn(C.c_void_p(x.data_ptr()), C.c_void_p(ref.data_ptr()), int(x.numel()),
+              float(cap) if cap is not None else 0.0, C.c_void_p(st.cuda_stream), C.byref(o)))
     return {f: getattr(o, f) for f, _ in FieldStats._fields_}
 
 
