@@ -544,13 +544,14 @@ def cycle_run(sysd, precision, model=None, every=1000, launch=None):
         if model is not None:
             handed.append(g.surrogate_count())
     en = g.energy()
+    stats = g.surrogate_stats() if model is not None else None
     g.close()
     share = None
     if model is not None:
         # facet-updates carried by the surrogate (counts sampled per window)
         share = float(np.mean([1.0 - h / F for h in handed]))
     return dict(value=F * total / (ms * 1e-3), ms=ms, steps=total, hist=hist,
-                energy_err=en["err"], surrogate_share=share)
+                energy_err=en["err"], surrogate_share=share, surrogate_stats=stats)
 
 
 def surrogate_case(args, sysd_tension, tune):
@@ -585,7 +586,7 @@ def surrogate_case(args, sysd_tension, tune):
            "train_loss": model.train_loss, "holdout_rmse_MPa": [float(v) for v in model.holdout_rmse],
            "dead_zone_MPa": [float(v) for v in model.y_dead],
            "capture_s": cap_s, "training_s": fit_s,
-           "gate": {"kappa_t": 0.8, "kappa_c": 0.9, "damage_max": 0.05}}
+           "gate": {"kappa_t": 1.1, "kappa_c": 0.9, "damage_max": 0.05}}
     r64 = cycle_run(cyl, "fp64")
     rmx = cycle_run(cyl, "mixed")
     rsg = cycle_run(cyl, "mixed", model=model)
@@ -599,6 +600,10 @@ def surrogate_case(args, sysd_tension, tune):
                      "stress_history_max_err_vs_fp64": float(np.abs(h - h64).max() / np.abs(h64).max())}
         if r["surrogate_share"] is not None:
             rec[name]["surrogate_share_of_facet_updates"] = r["surrogate_share"]
+            st = r["surrogate_stats"]
+            rec[name]["surrogate_counts"] = st
+            rec[name]["damaged_updates_share_by_network"] = (
+                st["damaged_network_updates"] / st["damaged_updates"] if st["damaged_updates"] else None)
         share = "" if r["surrogate_share"] is None else f", surrogate share {r['surrogate_share']:.3f}"
         log(f"cylinder {name}: {r['value']:.4e} facet-upd/s, peak +{h.max():.3f}/{h.min():.3f} MPa, "
             f"energy err {r['energy_err']:.2e}{share}")
@@ -797,6 +802,7 @@ def stress_history_run(sysd, precision, total, every, model=None, launch=None):
     if model is not None:
         out["surrogate_share"] = float(np.mean([1.0 - h / F for h in handed]))
         out["surrogate_share_at_end"] = 1.0 - handed[-1] / F
+        out["surrogate_stats"] = g.surrogate_stats()
     return out
 
 
@@ -814,6 +820,13 @@ def accuracy_vs(ref, run, name):
     if "surrogate_share" in run:
         rec["surrogate_share_of_facet_updates"] = run["surrogate_share"]
         rec["surrogate_share_at_end"] = run["surrogate_share_at_end"]
+        st = run["surrogate_stats"]
+        rec["surrogate_counts"] = st
+        rec["damaged_updates_share_by_network"] = (st["damaged_network_updates"] / st["damaged_updates"]
+                                                   if st["damaged_updates"] else None)
+        log(f"{name}: network carried {st['network_updates']} facet-updates, "
+            f"{st['damaged_network_updates']} of {st['damaged_updates']} damaged ones (1e-3 < D <= 0.05), "
+            f"{st['handed_back']} facets handed back")
     log(f"{name}: peak {h.max():.4f} MPa (fp64 {h0.max():.4f}), peak err {rec['peak_stress_err_vs_fp64']:.2e}, "
         f"history err {rec['stress_history_max_err_vs_fp64']:.2e}, energy err {rec['energy_balance_err']:.2e}")
     return rec

@@ -299,8 +299,9 @@ void ldpm_mlp_free(ldpm_mlp *m);
  * A facet is handed back to
  * the exact FP32 law for good (sticky flag) when
  *   - a feature leaves [box_lo, box_hi] (the trained range), or
- *   - tension: its effective strain reaches kappa_t e0(omega), or its e_max
- *     reaches kappa_t sigma_t / E0 (pre-peak envelope), or
+ *   - tension: its effective strain or its e_max reaches kappa_t e0(omega),
+ *     the elastic limit at the current angle (kappa_t > 1 keeps the facet
+ *     on the network past the peak, into softening), or
  *   - compression: -e_DV reaches kappa_c e_c0 or -t_N reaches kappa_c sigma_c0
  *     (onset of pore collapse), or
  *   - the damage D = 1 - t / (E0 e) of the surrogate's traction exceeds
@@ -319,6 +320,16 @@ typedef struct {
 ldpm_status ldpm_set_surrogate(ldpm_system *s, const ldpm_surrogate *sg);
 /* Number of facets handed back to the exact law so far. */
 ldpm_status ldpm_surrogate_count(ldpm_system *s, int64_t *n_exact);
+/* Running counts since ldpm_set_surrogate (synchronises): facets handed
+ * back, facet-updates made by the network, facet-updates whose damage
+ * D = 1 - t/(E0 e) of the new traction lies in (1e-3, damage_max] whichever
+ * law made them (the softening range the network may carry; below 1e-3 D
+ * is the rounding of an elastic update), and those of them the network
+ * made.  Integer counts, exact in any order.                               */
+typedef struct {
+    int64_t handed_back, network_updates, damaged_updates, damaged_network_updates;
+} ldpm_surrogate_counts;
+ldpm_status ldpm_surrogate_stats(ldpm_system *s, ldpm_surrogate_counts *out);
 
 /* ---- Capture of surrogate training samples from the FP64 exact law -------
  * While a capture is active (precision FP64, law 1), every step n with

@@ -1158,13 +1158,15 @@ ldpm_status ldpm_set_surrogate(ldpm_system* s, const ldpm_surrogate* g)
     for (int k = 0; k < MLP_NPARAM; k++)
         if (!std::isfinite(g->params[k])) return fail(LDPM_ERR_ARG, "surrogate: non-finite parameter %d", k);
     const size_t pbytes = ((size_t)MLP_NPARAM * 4 + 255) & ~size_t(255);
-    if (hipMalloc(&s->sg_mem, pbytes + (size_t)s->F) != hipSuccess) {
+    const size_t cbytes = 256;  // counters
+    if (hipMalloc(&s->sg_mem, pbytes + cbytes + (size_t)s->F) != hipSuccess) {
         s->sg_mem = nullptr;
         return fail(LDPM_ERR_ALLOC, "surrogate: allocation failed");
     }
     SurrogateArgs a{};
     a.params = (const float*)s->sg_mem;
-    a.flag = (uint8_t*)((char*)s->sg_mem + pbytes);
+    a.stats = (unsigned long long*)((char*)s->sg_mem + pbytes);
+    a.flag = (uint8_t*)((char*)s->sg_mem + pbytes + cbytes);
     for (int k = 0; k < MLP_IN; k++) {
         a.xmean[k] = g->x_mean[k];
         a.xscale[k] = g->x_scale[k];
@@ -1181,10 +1183,26 @@ ldpm_status ldpm_set_surrogate(ldpm_system* s, const ldpm_surrogate* g)
     a.ytau = g->y_tau;
     a.gate = GateArgs{g->kappa_t, g->kappa_c, g->damage_max};
     HIP_TRY(hipMemcpyAsync((void*)a.params, g->params, (size_t)MLP_NPARAM * 4, hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemsetAsync(a.flag, 0, (size_t)s->F, s->stream));
+    HIP_TRY(hipMemsetAsync(a.stats, 0, cbytes + (size_t)s->F, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->sg = a;
     s->sg_on = true;
+    return LDPM_OK;
+}
+
+ldpm_status ldpm_surrogate_stats(ldpm_system* s, ldpm_surrogate_counts* o)
+{
+    if (!s || !o) return fail(LDPM_ERR_ARG, "null argument");
+    if (!s->sg_on) return fail(LDPM_ERR_STATE, "no surrogate installed");
+    int64_t n = 0;
+    ldpm_status st = ldpm_surrogate_count(s, &n);
+    if (st != LDPM_OK) return st;
+    unsigned long long c[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpy(c, s->sg.stats, sizeof(c), hipMemcpyDeviceToHost));
+    o->handed_back = n;
+    o->network_updates = (int64_t)c[0];
+    o->damaged_updates = (int64_t)c[1];
+    o->damaged_network_updates = (int64_t)c[2];
     return LDPM_OK;
 }
 

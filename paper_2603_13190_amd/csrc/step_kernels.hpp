@@ -67,10 +67,18 @@ struct GateArgs {
 struct SurrogateArgs {
     const float* __restrict__ params;  // [MLP_NPARAM] FP32
     uint8_t* __restrict__ flag;        // [F] sticky: 1 = handed back to the exact law
+    // running counts of facet-updates: [0] by the network, [1] with damage
+    // in (SG_DAMAGED, damage_max] whichever law produced them, [2] those of
+    // [1] made by the network
+    unsigned long long* __restrict__ stats;
     float xmean[MLP_IN], xscale[MLP_IN], yscale[MLP_OUT], ydead[MLP_OUT], lo[MLP_IN], hi[MLP_IN];
     float ytau;
     GateArgs gate;
 };
+
+// a facet-update counts as damaged above this damage (below it D is the
+// rounding of an elastic update)
+constexpr float SG_DAMAGED = 1e-3f;
 
 struct CaptureArgs {
     float* __restrict__ rows;          // [cap][16]: x[9], residual[3], key (int64 bits)
@@ -115,17 +123,16 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap)
     return x * qn + (x < r ? x : r) + k;
 }
 
-// Is the facet inside the surrogate's envelope (the pre-peak elastic and
-// frictional regime the network is trained on)?  Tension: the effective
-// strain and e_max stay below kappa_t of the elastic limit e0(omega) (and of
-// sigma_t/E0 for e_max, whatever the angle); compression: -e_DV and -t_N stay
-// below kappa_c of the onset of pore collapse (e_c0, sigma_c0).
+// Is the facet inside the surrogate's envelope (the regime the network is
+// trained on)?  Tension: the effective strain and e_max stay below kappa_t
+// of the elastic limit e0(omega) at the current angle (kappa_t > 1 reaches
+// past the peak into softening, where the damage gate hands the facet back);
+// compression: -e_DV and -t_N stay below kappa_c of the onset of pore
+// collapse (e_c0, sigma_c0).
 template <typename R>
 __device__ __forceinline__ bool in_envelope(const MatDev<R>& p, const R e[3], R eV, const R told[3], R emax,
                                             const GateArgs& g)
 {
-    const R emax_lim = (R)g.kappa_t * p.sigma_t * p.inv_E0;
-    if (emax >= emax_lim) return false;
     if (e[0] > R(0)) {
         R sN, sT2, seff, seff2;
         int ex;
@@ -134,7 +141,8 @@ __device__ __forceinline__ bool in_envelope(const MatDev<R>& p, const R e[3], R 
         const R inv = R(1) / seff;
         const R sn = sN * inv, cs2 = p.alpha * sT2 * (inv * inv);
         const R sigma0 = R(2) * p.sigma_t / (sn + d_sqrt(sn * sn + p.c4 * cs2));
-        return eff < (R)g.kappa_t * sigma0 * p.inv_E0;
+        const R lim = (R)g.kappa_t * sigma0 * p.inv_E0;
+        return eff < lim && emax < lim;
     }
     const R eD = e[0] - eV;
     const R eDV = eV + p.beta * eD;
@@ -197,14 +205,20 @@ __device__ __forceinline__ MlpSmem<NW>& mlp_smem()
     return sm;
 }
 
+// per-lane counts of the surrogate's facet-updates (SurrogateArgs::stats)
+struct SgCount {
+    unsigned nn = 0, dmg = 0, dmg_nn = 0;
+};
+
 // One tile of TB tetrahedra (block-wide: every thread of a 12 TB block calls
 // it together).  do_prog: this block also evaluates the time programs.
+// cnt (surrogate mode): the lane's running counts.
 template <typename R, int LAW, int TB, int MODE>
 __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const NodeArgs& na, const FacetArgs<R>& fa,
                                            const MatDev<R>& mat, const int32_t* __restrict__ pos,
                                            R* __restrict__ contrib, double* __restrict__ wint,
                                            const ProgArgs& pr, int64_t step, double dt,
-                                           const SurrogateArgs& sg, const CaptureArgs& cp)
+                                           const SurrogateArgs& sg, const CaptureArgs& cp, SgCount* cnt = nullptr)
 {
     const int first = step == 0;
     constexpr int NS = 4 * TB;   // node slots per block
@@ -432,6 +446,16 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
             if (fvalid && fl && !sg.flag[f]) sg.flag[f] = 1;
         }
         if (exact) facet_law<R, LAW>(mat, len, e, de, eV, tv, emx);
+        if constexpr (MODE == MODE_SURROGATE) {
+            if (cnt && fvalid) {
+                // damage of the new traction, whichever law produced it
+                const float D = facet_damage(mat, e, tv);
+                const bool dmg = D > SG_DAMAGED && D <= sg.gate.damage_max;
+                cnt->nn += !exact;
+                cnt->dmg += dmg;
+                cnt->dmg_nn += dmg && !exact;
+            }
+        }
         if constexpr (MODE == MODE_CAPTURE) {
             if (fvalid && (f % cp.fstride) == cp.foff && (step % cp.sstride) == 0 &&
                 in_envelope(mat, e, eV, told, (R)fa.hemax[f], cp.gate) &&
@@ -548,8 +572,22 @@ __global__ __launch_bounds__(12 * TB) void k_facet_loop(NodeArgs na, FacetArgs<R
 {
     if constexpr (MODE == MODE_SURROGATE) mlp_load_bf16(sg.params, mlp_smem<12 * TB / 64>().W, threadIdx.x, 12 * TB);
     const int64_t nb = (na.T + TB - 1) / TB;
+    SgCount c;
     for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x)
-        facet_tile<R, LAW, TB, MODE>(blk, blk == 0, na, fa, mat, pos, contrib, wint, pr, step, dt, sg, cp);
+        facet_tile<R, LAW, TB, MODE>(blk, blk == 0, na, fa, mat, pos, contrib, wint, pr, step, dt, sg, cp, &c);
+    if constexpr (MODE == MODE_SURROGATE) {
+        // block totals (integer sums: exact in any order), then one atomic
+        // per counter and block
+        __shared__ unsigned s_cnt[3];
+        if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        if (c.nn) atomicAdd(&s_cnt[0], c.nn);
+        if (c.dmg) atomicAdd(&s_cnt[1], c.dmg);
+        if (c.dmg_nn) atomicAdd(&s_cnt[2], c.dmg_nn);
+        __syncthreads();
+        if (threadIdx.x < 3 && s_cnt[threadIdx.x])
+            atomicAdd(&sg.stats[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -25,7 +25,8 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_reaction", "ldpm_get_info", "ldpm_set_launch", "ldpm_get_launch", "ldpm_autotune",
            "ldpm_free", "ldpm_mlp_num_params", "ldpm_mlp_create", "ldpm_mlp_set_data",
            "ldpm_mlp_grad", "ldpm_mlp_train", "ldpm_mlp_forward", "ldpm_mlp_get_params",
-           "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_capture_begin",
+           "ldpm_mlp_free", "ldpm_set_surrogate", "ldpm_surrogate_count", "ldpm_surrogate_stats",
+           "ldpm_capture_begin",
            "ldpm_capture_end", "ldpm_crack_opening", "ldpm_volumetric_strain", "ldpm_compare_fields",
            "ldpm_compare_fields_noalloc",
            "ldpm_perturb", "ldpm_implicit_step", "ldpm_tessellate", "ldpm_element_lambda",
@@ -168,6 +169,7 @@ def lib():
         L.ldpm_mlp_free.restype = None
         L.ldpm_set_surrogate.argtypes = [C.c_void_p, C.POINTER(SurrogateDesc)]
         L.ldpm_surrogate_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.ldpm_surrogate_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64 * 4)]
         L.ldpm_capture_begin.argtypes = [C.c_void_p, C.POINTER(CaptureOpts)]
         L.ldpm_capture_end.argtypes = [C.c_void_p, _fp, C.c_int64, C.POINTER(C.c_int64)]
         L.ldpm_crack_opening.argtypes = [C.c_void_p, C.c_void_p]
@@ -442,7 +444,7 @@ class System:
         return as_dict(best), us.value, trials
 
     def set_surrogate(self, params, x_mean, x_scale, y_scale, box_lo, box_hi,
-                      kappa_t=0.8, kappa_c=0.9, damage_max=0.05, y_dead=(0.0, 0.0, 0.0), y_tau=0.0):
+                      kappa_t=1.1, kappa_c=0.9, damage_max=0.05, y_dead=(0.0, 0.0, 0.0), y_tau=0.0):
         """Install the MLP surrogate of the facet law (None removes it)."""
         if params is None:
             _check(lib().ldpm_set_surrogate(self.h, None))
@@ -464,8 +466,16 @@ class System:
         _check(lib().ldpm_surrogate_count(self.h, C.byref(n)))
         return int(n.value)
 
+    def surrogate_stats(self):
+        """Running counts since the surrogate was installed: facets handed
+        back, facet-updates by the network, damaged facet-updates (damage in
+        (1e-3, damage_max]) by either law, and those of them by the network."""
+        c = (C.c_int64 * 4)()
+        _check(lib().ldpm_surrogate_stats(self.h, C.byref(c)))
+        return dict(handed_back=c[0], network_updates=c[1], damaged_updates=c[2], damaged_network_updates=c[3])
+
     def capture_begin(self, capacity, facet_stride=1, facet_offset=0, step_stride=1,
-                      kappa_t=0.8, kappa_c=0.9, damage_max=0.05):
+                      kappa_t=1.1, kappa_c=0.9, damage_max=0.05):
         o = CaptureOpts(int(capacity), int(facet_stride), int(facet_offset), int(step_stride),
                         float(kappa_t), float(kappa_c), float(damage_max))
         self._cap = int(capacity)

@@ -42,14 +42,14 @@ class Model:
     holdout_rmse: np.ndarray = None
     n_train: int = 0
 
-    def install(self, system, kappa_t=0.8, kappa_c=0.9, damage_max=0.05):
+    def install(self, system, kappa_t=1.1, kappa_c=0.9, damage_max=0.05):
         system.set_surrogate(self.params, self.x_mean, self.x_scale, self.y_scale,
                              self.box_lo, self.box_hi, kappa_t, kappa_c, damage_max, self.y_dead,
                              self.y_tau)
 
 
 def capture(sysd, steps, facet_stride=7, step_stride=50, capacity=2_000_000, seed_offset=0,
-            kappa_t=0.8, kappa_c=0.9, damage_max=0.05):
+            kappa_t=1.1, kappa_c=0.9, damage_max=0.05):
     """Run the FP64 solver for `steps` and record in-envelope samples."""
     g = ldpm.System(sysd, precision="fp64")
     g.capture_begin(capacity, facet_stride, seed_offset % facet_stride, step_stride,

@@ -325,7 +325,7 @@ def test_autotune_is_refused_with_a_surrogate_or_a_capture():
     assert ei.value.status == LDPM_ERR_STATE
     assert g.read_state()["step"] == 10
     c = gpu(s, precision="fp64")
-    c.capture_begin(1000, facet_stride=50, facet_offset=0, step_stride=5, kappa_t=0.8, kappa_c=0.9,
+    c.capture_begin(1000, facet_stride=50, facet_offset=0, step_stride=5, kappa_t=1.1, kappa_c=0.9,
                     damage_max=0.05)
     c.step(10)
     with pytest.raises(LdpmError) as ei:
