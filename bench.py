@@ -742,6 +742,23 @@ def window_run(sysd, precision, start, warmup, steps, tune, profile_steps, key=N
     return r
 
 
+def stream_reference(gib=2.0, reps=10):
+    """HBM bandwidth that plain streaming kernels reach on this GPU (torch's
+    device copy, read-only reduction and fill of `gib` GiB), measured with
+    events: the practical ceiling beside the nominal peak."""
+    import torch
+    n = int(gib * 2 ** 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    out = {"size_GiB": gib}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 16 * n), ("read", lambda: x.sum(), 8 * n),
+                             ("write", lambda: y.fill_(1.0), 8 * n)):
+        out[f"{name}_GBs"] = nbytes / (time_on_stream(fn, reps) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline_of(r, F, precision):
     """The roofline object of the facet kernel (the dominant kernel)."""
     bts = r["facet_kernel_bytes"]
@@ -765,16 +782,20 @@ def roofline_of(r, F, precision):
     }
 
 
-def stress_history_run(sysd, precision, total, every, model=None, launch=None):
+def stress_history_run(sysd, precision, total, every, model=None, launch=None, tune=None):
     """`total` steps from the initial state, the nominal stress (loaded
     face's reaction over the nominal area) and W_kin/W_int every `every`
     steps; the energies at the end; timing of the stepping (sampling
-    outside the timed spans); the surrogate's share of facet-updates."""
+    outside the timed spans); the surrogate's share of facet-updates.
+    tune: steps per autotuner trial before the run (the tuner restores the
+    state, so the trajectory is unchanged)."""
     import torch
     from paper_2603_13190_amd.ldpm import System
     g = System(sysd, precision=precision)
     if launch:
         g.set_launch(**dict(launch, persistent=0))
+    if tune:
+        g.autotune(steps_per_trial=tune)
     if model is not None:
         model.install(g)
     prog, area = sysd["meta"]["load_prog"], sysd["meta"]["area"]
@@ -839,8 +860,9 @@ def tension_accuracy(ten, args):
     the quasi-static ratio W_kin/W_int."""
     total = ten["meta"]["n_steps"] if args.tension_steps is None else args.tension_steps
     every = max(1, total // 200)
-    r64 = stress_history_run(ten, "fp64", total, every)
-    rmx = stress_history_run(ten, "mixed", total, every)
+    tune = None if args.no_tune else args.tune_steps
+    r64 = stress_history_run(ten, "fp64", total, every, tune=tune)
+    rmx = stress_history_run(ten, "mixed", total, every, tune=tune)
     h = r64["hist"]
     ip = int(np.argmax(h))
     rec = {"workload": "tension_cube100: " + TENSION_DESC, "steps": total, "sample_every": every,
@@ -851,6 +873,7 @@ def tension_accuracy(ten, args):
            "fp64_value": r64["value"],
            "quasi_static": {"kin_over_int_max_after_ramp": float(np.nanmax(r64["kin"][len(h) // 10:])),
                             "kin_over_int_end": float(r64["kin"][-1])},
+           "launch_fp64": r64["g"].get_launch(), "launch_mixed": rmx["g"].get_launch(),
            "mixed": accuracy_vs(r64, rmx, "tension cube mixed vs fp64")}
     rec["mixed"]["speedup_vs_fp64_whole_trajectory"] = rmx["value"] / r64["value"]
     log(f"tension cube: peak {h.max():.4f} MPa at step {(ip + 1) * every}, end {h[-1]:.4f} MPa, "
@@ -1065,6 +1088,15 @@ def main():
                      "generation_s": m.get("generation_s")}
     out["energy_balance_err"] = h64["energy_err"]
     out["roofline"] = roofline_of(h64, F, "fp64")
+    # (not in counter runs: its copy would be taken for the calibration copy)
+    ref = stream_reference() if args.copy_calibration <= 0 else None
+    if ref is not None:
+        out["roofline"]["stream_reference"] = dict(
+            ref, facet_kernel_vs_copy=out["roofline"]["achieved"] / ref["copy_GBs"],
+            note="plain streaming kernels on this GPU (torch copy, sum, fill): the practical ceiling beside the "
+                 "8 TB/s peak")
+        log(f"stream reference: copy {ref['copy_GBs']:.0f} GB/s, read {ref['read_GBs']:.0f} GB/s, "
+            f"write {ref['write_GBs']:.0f} GB/s")
     if not args.no_mixed:
         hmx = window_run(sysd, "mixed", start, args.warmup, args.steps, tune, args.profile_steps)
         out["mixed"] = {"value": hmx["value"], "ms_per_step": hmx["ms_per_step"],
