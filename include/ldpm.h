@@ -325,9 +325,12 @@ ldpm_status ldpm_surrogate_count(ldpm_system *s, int64_t *n_exact);
  * D = 1 - t/(E0 e) of the new traction lies in (1e-3, damage_max] whichever
  * law made them (the softening range the network may carry; below 1e-3 D
  * is the rounding of an elastic update), and those of them the network
- * made.  Integer counts, exact in any order.                               */
+ * made; and the facets handed back by each gate: the strain envelope, the
+ * trained feature box (facets inside the envelope), the damage limit.
+ * Integer counts, exact in any order.                                      */
 typedef struct {
     int64_t handed_back, network_updates, damaged_updates, damaged_network_updates;
+    int64_t handed_back_envelope, handed_back_box, handed_back_damage;
 } ldpm_surrogate_counts;
 ldpm_status ldpm_surrogate_stats(ldpm_system *s, ldpm_surrogate_counts *out);
 

@@ -1197,12 +1197,15 @@ ldpm_status ldpm_surrogate_stats(ldpm_system* s, ldpm_surrogate_counts* o)
     int64_t n = 0;
     ldpm_status st = ldpm_surrogate_count(s, &n);
     if (st != LDPM_OK) return st;
-    unsigned long long c[3] = {0, 0, 0};
+    unsigned long long c[SG_NSTATS] = {};
     HIP_TRY(hipMemcpy(c, s->sg.stats, sizeof(c), hipMemcpyDeviceToHost));
     o->handed_back = n;
     o->network_updates = (int64_t)c[0];
     o->damaged_updates = (int64_t)c[1];
     o->damaged_network_updates = (int64_t)c[2];
+    o->handed_back_envelope = (int64_t)c[3];
+    o->handed_back_box = (int64_t)c[4];
+    o->handed_back_damage = (int64_t)c[5];
     return LDPM_OK;
 }
 

@@ -69,7 +69,8 @@ struct SurrogateArgs {
     uint8_t* __restrict__ flag;        // [F] sticky: 1 = handed back to the exact law
     // running counts of facet-updates: [0] by the network, [1] with damage
     // in (SG_DAMAGED, damage_max] whichever law produced them, [2] those of
-    // [1] made by the network
+    // [1] made by the network; facets handed back [3] by the strain
+    // envelope, [4] by the feature box, [5] by the damage gate
     unsigned long long* __restrict__ stats;
     float xmean[MLP_IN], xscale[MLP_IN], yscale[MLP_OUT], ydead[MLP_OUT], lo[MLP_IN], hi[MLP_IN];
     float ytau;
@@ -79,6 +80,7 @@ struct SurrogateArgs {
 // a facet-update counts as damaged above this damage (below it D is the
 // rounding of an elastic update)
 constexpr float SG_DAMAGED = 1e-3f;
+constexpr int SG_NSTATS = 6;
 
 struct CaptureArgs {
     float* __restrict__ rows;          // [cap][16]: x[9], residual[3], key (int64 bits)
@@ -208,6 +210,9 @@ __device__ __forceinline__ MlpSmem<NW>& mlp_smem()
 // per-lane counts of the surrogate's facet-updates (SurrogateArgs::stats)
 struct SgCount {
     unsigned nn = 0, dmg = 0, dmg_nn = 0;
+    // facets handed back by the strain envelope, by the trained feature box
+    // (inside the envelope), by the damage gate
+    unsigned out_env = 0, out_box = 0, out_dmg = 0;
 };
 
 // One tile of TB tetrahedra (block-wide: every thread of a 12 TB block calls
@@ -392,10 +397,15 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                 fl = sg.flag[f];
                 fr = surrogate_features(mat, e, de, told, x);
                 if (!fl) {
-                    bool ok = in_envelope(mat, e, eV, told, emx, sg.gate);
+                    const bool env = in_envelope(mat, e, eV, told, emx, sg.gate);
+                    bool box = true;
 #pragma unroll
-                    for (int k = 0; k < MLP_IN; k++) ok = ok && x[k] >= sg.lo[k] && x[k] <= sg.hi[k];
-                    if (!ok) fl = 1;
+                    for (int k = 0; k < MLP_IN; k++) box = box && x[k] >= sg.lo[k] && x[k] <= sg.hi[k];
+                    if (!(env && box)) fl = 1;
+                    if (cnt) {
+                        cnt->out_env += !env;
+                        cnt->out_box += env && !box;
+                    }
                 }
             }
             const bool use_nn = fvalid && !fl;
@@ -428,6 +438,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                     tn[2] = told[2] + mat.aE0 * de[2] + (R)rL;
                     if (facet_damage(mat, e, tn) > sg.gate.damage_max) {
                         fl = 1;  // leaves the envelope: exact law from now on
+                        if (cnt) cnt->out_dmg += 1;
                     } else {
                         tv[0] = tn[0];
                         tv[1] = tn[1];
@@ -578,14 +589,15 @@ __global__ __launch_bounds__(12 * TB) void k_facet_loop(NodeArgs na, FacetArgs<R
     if constexpr (MODE == MODE_SURROGATE) {
         // block totals (integer sums: exact in any order), then one atomic
         // per counter and block
-        __shared__ unsigned s_cnt[3];
-        if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+        __shared__ unsigned s_cnt[SG_NSTATS];
+        if (threadIdx.x < SG_NSTATS) s_cnt[threadIdx.x] = 0;
         __syncthreads();
-        if (c.nn) atomicAdd(&s_cnt[0], c.nn);
-        if (c.dmg) atomicAdd(&s_cnt[1], c.dmg);
-        if (c.dmg_nn) atomicAdd(&s_cnt[2], c.dmg_nn);
+        const unsigned v[SG_NSTATS] = {c.nn, c.dmg, c.dmg_nn, c.out_env, c.out_box, c.out_dmg};
+#pragma unroll
+        for (int k = 0; k < SG_NSTATS; k++)
+            if (v[k]) atomicAdd(&s_cnt[k], v[k]);
         __syncthreads();
-        if (threadIdx.x < 3 && s_cnt[threadIdx.x])
+        if (threadIdx.x < SG_NSTATS && s_cnt[threadIdx.x])
             atomicAdd(&sg.stats[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
     }
 }

@@ -169,7 +169,7 @@ def lib():
         L.ldpm_mlp_free.restype = None
         L.ldpm_set_surrogate.argtypes = [C.c_void_p, C.POINTER(SurrogateDesc)]
         L.ldpm_surrogate_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
-        L.ldpm_surrogate_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64 * 4)]
+        L.ldpm_surrogate_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64 * 7)]
         L.ldpm_capture_begin.argtypes = [C.c_void_p, C.POINTER(CaptureOpts)]
         L.ldpm_capture_end.argtypes = [C.c_void_p, _fp, C.c_int64, C.POINTER(C.c_int64)]
         L.ldpm_crack_opening.argtypes = [C.c_void_p, C.c_void_p]
@@ -469,10 +469,13 @@ class System:
     def surrogate_stats(self):
         """Running counts since the surrogate was installed: facets handed
         back, facet-updates by the network, damaged facet-updates (damage in
-        (1e-3, damage_max]) by either law, and those of them by the network."""
-        c = (C.c_int64 * 4)()
+        (1e-3, damage_max]) by either law, those of them by the network, and
+        the facets handed back by the envelope, the feature box, the damage
+        gate."""
+        c = (C.c_int64 * 7)()
         _check(lib().ldpm_surrogate_stats(self.h, C.byref(c)))
-        return dict(handed_back=c[0], network_updates=c[1], damaged_updates=c[2], damaged_network_updates=c[3])
+        return dict(handed_back=c[0], network_updates=c[1], damaged_updates=c[2], damaged_network_updates=c[3],
+                    handed_back_envelope=c[4], handed_back_box=c[5], handed_back_damage=c[6])
 
     def capture_begin(self, capacity, facet_stride=1, facet_offset=0, step_stride=1,
                       kappa_t=1.1, kappa_c=0.9, damage_max=0.05):

@@ -127,6 +127,7 @@ def test_surrogate_end_to_end_accuracy_and_sticky_gate():
     assert all(b >= a for a, b in zip(counts, counts[1:]))
     assert counts[0] < F                         # the surrogate does carry facets
     assert st["handed_back"] == counts[-1]
+    assert st["handed_back_envelope"] + st["handed_back_box"] + st["handed_back_damage"] == st["handed_back"]
     # the network carries facets into softening (damage up to damage_max)
     assert st["damaged_network_updates"] > 0
     # the surrogate form's bar: peak stress within 1 %, energy balance within
