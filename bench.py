@@ -83,6 +83,7 @@ def timed_run(sysd, precision, warmup, steps, launch=None, tune=None):
         g.tuned = dict(best=best, us_per_step=us, trials=len(trials),
                        worst_us_per_step=max(t[1] for t in trials) if trials else us)
         log(f"autotune ({precision}): best {best} at {us:.2f} us/step over {len(trials)} shapes")
+        g.step(SETTLE_STEPS)  # uninterrupted work before the warmup (clocks)
     g.step(warmup)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -686,6 +687,7 @@ def window_case(sysd, workload, runs, warmup, steps, tune, field=None, key=None)
 
 
 
+SETTLE_STEPS = 300
 CYL_DESC = ("cylinder 100 x 200 mm, d {d0:g}-{da:g} mm Fuller 0.4, seed 1, tension-compression cycles "
             "(bottom u_z fixed, top u_z triangle wave at 0.2 /s between +1.2e-4 and -1e-3 strain), full law")
 SURVEY_BYTES = {"fp64": 338.0, "mixed": 174.0}
@@ -694,21 +696,27 @@ SURVEY_BYTES = {"fp64": 338.0, "mixed": 174.0}
 def window_run(sysd, precision, start, warmup, steps, tune, profile_steps, key=None):
     """Throughput of `steps` explicit steps timed after `start` + `warmup`
     untimed steps from the initial state (torch events on the library's
-    stream), the launch shape chosen by the autotuner at the window's start,
-    and the facet kernel's average launch time from HIP events recorded by
-    the dispatches themselves (ldpm_step_profiled, after the timed steps)."""
+    stream), the launch shape chosen by the autotuner shortly before the
+    window's start, and the facet kernel's average launch time from HIP
+    events recorded by the dispatches themselves (ldpm_step_profiled, after
+    the timed steps)."""
     import torch
     from paper_2603_13190_amd.ldpm import System
     m = sysd["meta"]
     F = m["F"]
     g = System(sysd, precision=precision)
-    g.step(start)
+    # the autotuner runs SETTLE steps before the window's start, so that the
+    # warmup and the timed steps follow uninterrupted work (after the
+    # tuner's pause the GPU's clocks need some milliseconds to come back)
+    settle = min(start, SETTLE_STEPS) if tune else 0
+    g.step(start - settle)
     r = {"precision": precision}
     if tune:
         best, us, trials = g.autotune(steps_per_trial=tune)
         r["autotune"] = dict(best=best, us_per_step=us, trials=len(trials),
                              worst_us_per_step=max(t[1] for t in trials) if trials else us)
         log(f"autotune ({precision}): best {best} at {us:.2f} us/step over {len(trials)} shapes")
+    g.step(settle)
     g.step(warmup)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
