@@ -114,6 +114,21 @@ struct ParticleArgs {
 // ---------------------------------------------------------------------------
 // facet kernel
 // ---------------------------------------------------------------------------
+// Facet records and the traction history are touched once per step, in facet
+// order: they are loaded and stored nontemporally, so that they do not evict
+// what the step reuses from L2 (node records and edge frames, gathered by
+// every tet around them, and the tet-node sums the particle kernel reads).
+template <typename T>
+__device__ __forceinline__ T ld_once(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_once(T v, T* p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap)
 {
     // Blocks are dispatched round-robin over the 8 XCDs (each with its own
@@ -253,17 +268,17 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     R emx = R(0);
     if (fvalid) {
         const int64_t F = fa.F, E = fa.E;
-        rc = fa.rec[f];
+        rc = ld_once(&fa.rec[f]);
         const int64_t r = rc & 0x0fffffff;
         const R* fr = fa.frame + r * 8;
         n0 = fr[0]; n1 = fr[1]; n2 = fr[2];
         m0 = fr[3]; m1 = fr[4]; m2 = fr[5];
         len = fr[6];
         ilen = fr[7];
-        cI0 = fa.cI[f]; cI1 = fa.cI[F + f]; cI2 = fa.cI[2 * F + f];
-        A = fa.area[f];
-        tv[0] = fa.ht[f]; tv[1] = fa.ht[F + f]; tv[2] = fa.ht[2 * F + f];
-        if (LAW != 0) emx = fa.hemax[f];
+        cI0 = ld_once(&fa.cI[f]); cI1 = ld_once(&fa.cI[F + f]); cI2 = ld_once(&fa.cI[2 * F + f]);
+        A = ld_once(&fa.area[f]);
+        tv[0] = ld_once(&fa.ht[f]); tv[1] = ld_once(&fa.ht[F + f]); tv[2] = ld_once(&fa.ht[2 * F + f]);
+        if (LAW != 0) emx = ld_once(&fa.hemax[f]);
     }
     // output position (incidence order) of the tet-node sums of phase D, and
     // the tet's accumulated internal work
@@ -495,10 +510,10 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
             }
         }
         if (fvalid) {
-            fa.ht[f] = tv[0];
-            fa.ht[F + f] = tv[1];
-            fa.ht[2 * F + f] = tv[2];
-            if (LAW != 0) fa.hemax[f] = emx;
+            st_once(tv[0], &fa.ht[f]);
+            st_once(tv[1], &fa.ht[F + f]);
+            st_once(tv[2], &fa.ht[2 * F + f]);
+            if (LAW != 0) st_once(emx, &fa.hemax[f]);
             // internal work A l (t_old + t)/2 . de
             wk = (double)(A * len * R(0.5) *
                           ((told[0] + tv[0]) * de[0] + (told[1] + tv[1]) * de[1] + (told[2] + tv[2]) * de[2]));
