@@ -751,18 +751,25 @@ def window_run(sysd, precision, start, warmup, steps, tune, profile_steps, key=N
 
 
 def stream_reference(gib=2.0, reps=10):
-    """HBM bandwidth that plain streaming kernels reach on this GPU (torch's
-    device copy, read-only reduction and fill of `gib` GiB), measured with
-    events: the practical ceiling beside the nominal peak."""
+    """HBM bandwidth that plain streaming kernels reach on this GPU, measured
+    with events: the library's reference kernels (one 16-byte element per
+    lane, one pass, nontemporal; copy, read-only, fill and a three-read /
+    two-write mix over `gib` GiB per array) and, for comparison, torch's
+    device copy.  The practical ceiling beside the nominal peak."""
     import torch
-    n = int(gib * 2 ** 30) // 8
-    x = torch.ones(n, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    out = {"size_GiB": gib}
-    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 16 * n), ("read", lambda: x.sum(), 8 * n),
-                             ("write", lambda: y.fill_(1.0), 8 * n)):
+    from paper_2603_13190_amd.ldpm import stream_probe
+    n = int(gib * 2 ** 30) // 16 * 16
+    a = torch.ones(3 * n // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty(2 * n // 8, dtype=torch.float64, device="cuda")
+    x, y = a[:n // 8], b[:n // 8]
+    out = {"size_GiB": gib, "kind": "library reference kernels (16 B per lane, one pass, nontemporal)"}
+    for name, fn, nbytes in (("copy", lambda: stream_probe("copy", x, y, 2 * n), 2 * n),
+                             ("read", lambda: stream_probe("read", x, b, n), n),
+                             ("write", lambda: stream_probe("fill", None, y, n), n),
+                             ("mix_3r2w", lambda: stream_probe("mix", a, b, 5 * n), 5 * n)):
         out[f"{name}_GBs"] = nbytes / (time_on_stream(fn, reps) * 1e-3) / 1e9
-    del x, y
+    out["torch_copy_GBs"] = 2 * n / (time_on_stream(lambda: y.copy_(x), reps) * 1e-3) / 1e9
+    del a, b, x, y
     torch.cuda.empty_cache()
     return out
 
@@ -1101,10 +1108,11 @@ def main():
     if ref is not None:
         out["roofline"]["stream_reference"] = dict(
             ref, facet_kernel_vs_copy=out["roofline"]["achieved"] / ref["copy_GBs"],
-            note="plain streaming kernels on this GPU (torch copy, sum, fill): the practical ceiling beside the "
-                 "8 TB/s peak")
+            facet_kernel_vs_mix=out["roofline"]["achieved"] / ref["mix_3r2w_GBs"],
+            note="plain streaming kernels on this GPU: the practical ceiling beside the 8 TB/s peak")
         log(f"stream reference: copy {ref['copy_GBs']:.0f} GB/s, read {ref['read_GBs']:.0f} GB/s, "
-            f"write {ref['write_GBs']:.0f} GB/s")
+            f"write {ref['write_GBs']:.0f} GB/s, 3r2w {ref['mix_3r2w_GBs']:.0f} GB/s, "
+            f"torch copy {ref['torch_copy_GBs']:.0f} GB/s")
     if not args.no_mixed:
         hmx = window_run(sysd, "mixed", start, args.warmup, args.steps, tune, args.profile_steps)
         out["mixed"] = {"value": hmx["value"], "ms_per_step": hmx["ms_per_step"],

@@ -551,6 +551,25 @@ typedef struct {
 } ldpm_elem_desc;
 ldpm_status ldpm_element_lambda(const ldpm_elem_desc *desc, double *lam, void *stream);
 
+/* Reference streaming kernels, for measurement: the HBM bandwidth that
+ * plain coalesced traffic reaches on the device, the practical ceiling that
+ * the step's kernels are compared with beside the nominal peak.  Enqueues
+ * ONE launch on `stream` (hipStream_t or NULL) and returns; the caller times
+ * it (events on the same stream).  One 16-byte element per lane, one pass,
+ * nontemporal loads and stores.  DEVICE buffers owned by the caller,
+ * 16-byte aligned; `bytes` is the traffic the launch moves:
+ *   LDPM_STREAM_COPY: reads bytes/2 from src, writes them to dst;
+ *   LDPM_STREAM_READ: reads `bytes` from src, writes one double per 4 KiB
+ *                     block of src to dst (dst holds bytes/512 bytes);
+ *   LDPM_STREAM_FILL: writes `bytes` to dst (src unused, may be NULL);
+ *   LDPM_STREAM_MIX:  three reads and two writes per element: reads 3/5 of
+ *                     `bytes` from src, writes 2/5 to dst.
+ * Errors: LDPM_ERR_ARG for an unknown kind, null or misaligned buffers, or
+ * bytes not a positive multiple of 32 (COPY), 16 (READ, FILL) or 80 (MIX);
+ * LDPM_ERR_DEVICE if the launch fails. */
+enum { LDPM_STREAM_COPY = 0, LDPM_STREAM_READ = 1, LDPM_STREAM_FILL = 2, LDPM_STREAM_MIX = 3 };
+ldpm_status ldpm_stream_probe(int kind, const void *src, void *dst, int64_t bytes, void *stream);
+
 /* Release device memory and the handle (NULL is a no-op). */
 void ldpm_free(ldpm_system *s);
 

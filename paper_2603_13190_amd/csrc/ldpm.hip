@@ -87,6 +87,7 @@ ldpm_status ldpm_fail(ldpm_status st, const char* fmt, ...)
 #include "implicit.hpp"
 #include "tessellate.hpp"
 #include "bound.hpp"
+#include "stream_ref.hpp"
 
 // ---------------------------------------------------------------------------
 // host side
@@ -1422,6 +1423,35 @@ ldpm_status ldpm_compare_fields(const double* x, const double* ref, int64_t n, d
         return fail(LDPM_ERR_ALLOC, "compare_fields: hipMalloc(%zu) failed", CMP_BUF_BYTES);
     }
     return cmp_run(x, ref, n, cap, (hipStream_t)stream, mem, out);
+}
+
+ldpm_status ldpm_stream_probe(int kind, const void* src, void* dst, int64_t bytes, void* stream)
+{
+    if (kind < LDPM_STREAM_COPY || kind > LDPM_STREAM_MIX)
+        return fail(LDPM_ERR_ARG, "stream_probe: unknown kind %d", kind);
+    // bytes moved per 16-byte element of each stream
+    const int64_t unit = kind == LDPM_STREAM_MIX ? 80 : (kind == LDPM_STREAM_COPY ? 32 : 16);
+    if (bytes <= 0 || bytes % unit != 0)
+        return fail(LDPM_ERR_ARG, "stream_probe: bytes must be a positive multiple of %lld", (long long)unit);
+    if ((kind != LDPM_STREAM_FILL && !src) || !dst)
+        return fail(LDPM_ERR_ARG, "stream_probe: null buffer");
+    if ((kind != LDPM_STREAM_FILL && ((uintptr_t)src & 15)) || ((uintptr_t)dst & 15))
+        return fail(LDPM_ERR_ARG, "stream_probe: buffers must be 16-byte aligned");
+    const int64_t n = bytes / unit;  // elements per stream
+    const int64_t blocks = (n + STREAM_THREADS - 1) / STREAM_THREADS;
+    if (blocks > 0x7fffffffll) return fail(LDPM_ERR_ARG, "stream_probe: bytes too large");
+    hipStream_t st = (hipStream_t)stream;
+    const auto* a = (const stream_d2*)src;
+    auto* b = (stream_d2*)dst;
+    switch (kind) {
+    case LDPM_STREAM_COPY: k_stream_copy<<<(unsigned)blocks, STREAM_THREADS, 0, st>>>(a, b, n); break;
+    case LDPM_STREAM_READ: k_stream_read<<<(unsigned)blocks, STREAM_THREADS, 0, st>>>(a, (double*)dst, n); break;
+    case LDPM_STREAM_FILL: k_stream_fill<<<(unsigned)blocks, STREAM_THREADS, 0, st>>>(b, n); break;
+    default: k_stream_mix<<<(unsigned)blocks, STREAM_THREADS, 0, st>>>(a, b, n); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LDPM_ERR_DEVICE, "stream_probe: %s", hipGetErrorString(e));
+    return LDPM_OK;
 }
 
 ldpm_status ldpm_compare_fields_noalloc(const double* x, const double* ref, int64_t n, double cap, void* stream,

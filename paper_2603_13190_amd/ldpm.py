@@ -30,7 +30,7 @@ EXPORTS = ("ldpm_load_system", "ldpm_step", "ldpm_step_profiled", "ldpm_sync", "
            "ldpm_capture_end", "ldpm_crack_opening", "ldpm_volumetric_strain", "ldpm_compare_fields",
            "ldpm_compare_fields_noalloc",
            "ldpm_perturb", "ldpm_implicit_step", "ldpm_tessellate", "ldpm_element_lambda",
-           "ldpm_last_error")
+           "ldpm_stream_probe", "ldpm_last_error")
 
 _MAT_FIELDS = ("E0", "alpha", "sigma_t", "l_t", "r_st", "n_t", "r_s", "k_t",
                "sigma_c0", "Hc0_over_E0", "Hc1_over_E0", "kc0", "kc1", "kc2", "kc3",
@@ -180,6 +180,7 @@ def lib():
         L.ldpm_perturb.argtypes = [C.c_void_p, _dp, _dp]
         L.ldpm_implicit_step.argtypes = [C.c_void_p, C.POINTER(ImplicitOpts), C.c_int64,
                                          C.POINTER(ImplicitStats)]
+        L.ldpm_stream_probe.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.ldpm_free.argtypes = [C.c_void_p]
         L.ldpm_free.restype = None
         L.ldpm_last_error.restype = C.c_char_p
@@ -648,6 +649,22 @@ class ElemDesc(C.Structure):
     _fields_ = [("n_particles", C.c_int64), ("n_tets", C.c_int64), ("tet_nodes", _ip), ("facet_I", _ip),
                 ("facet_J", _ip), ("facet_cI", _dp), ("facet_n", _dp), ("facet_area", _dp), ("facet_len", _dp),
                 ("share", _dp), ("E0", C.c_double), ("alpha", C.c_double)]
+
+
+STREAM_KINDS = {"copy": 0, "read": 1, "fill": 2, "mix": 3}
+
+
+def stream_probe(kind, src, dst, nbytes, stream=None):
+    """Enqueue one reference streaming kernel (ldpm_stream_probe) moving
+    nbytes between the device tensors src and dst (src may be None for
+    "fill"); the caller times it on `stream` (default: torch's current)."""
+    import torch
+    for t in (src, dst):
+        if t is not None and not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("buffers must be contiguous device tensors")
+    st = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().ldpm_stream_probe(STREAM_KINDS[kind], C.c_void_p(src.data_ptr() if src is not None else 0),
+                                   C.c_void_p(dst.data_ptr()), int(nbytes), C.c_void_p(st.cuda_stream)))
 
 
 def element_lambda_max(sysd, E0, alpha, share, stream=None):
