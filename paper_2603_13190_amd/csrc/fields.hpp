@@ -29,10 +29,10 @@ __device__ __forceinline__ FacetGeo facet_geo(const FacetArgs<R>& fa, const int3
     for (int c = 0; c < 3; c++) {
         g.n[c] = (double)fr[c];
         g.m[c] = (double)fr[3 + c];
-        g.cI[c] = (double)fa.cI[c * F + f];
+        g.cI[c] = (double)fa.geo[quad_index<R>(F, f, c)];
     }
     g.len = (double)fr[6];
-    g.area = (double)fa.area[f];
+    g.area = (double)fa.geo[quad_index<R>(F, f, 3)];
     g.l[0] = g.n[1] * g.m[2] - g.n[2] * g.m[1];
     g.l[1] = g.n[2] * g.m[0] - g.n[0] * g.m[2];
     g.l[2] = g.n[0] * g.m[1] - g.n[1] * g.m[0];
@@ -97,8 +97,8 @@ __global__ __launch_bounds__(12 * TB) void k_crack(NodeArgs na, FacetArgs<R> fa,
         for (int c = 0; c < 3; c++) {
             n[c] = (double)fr[c];
             m[c] = (double)fr[3 + c];
-            cI[c] = (double)fa.cI[c * F + f];
-            t[c] = (double)fa.ht[c * F + f];
+            cI[c] = (double)fa.geo[quad_index<R>(F, f, c)];
+            t[c] = (double)fa.hist[quad_index<R>(F, f, c)];
         }
         len = (double)fr[6];
     }
@@ -220,18 +220,18 @@ __global__ __launch_bounds__(256) void k_jump(NodeArgs na, FacetArgs<R> fa, MatD
         for (int c = 0; c < 3; c++) {
             er[c] = (R)(e[c] + de[c]);
             der[c] = (R)de[c];
-            tv[c] = fa.ht[c * F + f];
+            tv[c] = fa.hist[quad_index<R>(F, f, c)];
             told[c] = tv[c];
         }
-        R em = LAW != 0 ? fa.hemax[f] : R(0);
+        R em = fa.hist[quad_index<R>(F, f, 3)];
         facet_law<R, LAW>(mat, (R)g.len, er, der, eV, tv, em);
         double w = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; c++) w += 0.5 * ((double)told[c] + (double)tv[c]) * de[c];
         W += g.area * g.len * w;
 #pragma unroll
-        for (int c = 0; c < 3; c++) fa.ht[c * F + f] = tv[c];
-        if (LAW != 0) fa.hemax[f] = em;
+        for (int c = 0; c < 3; c++) fa.hist[quad_index<R>(F, f, c)] = tv[c];
+        fa.hist[quad_index<R>(F, f, 3)] = em;
     }
     wint[t] += W;
     wj[t] = W;

@@ -106,11 +106,11 @@ __global__ __launch_bounds__(256) void k_im_block_k0(const FacetArgs<R> fa, cons
         const double len = (double)fr[6];
         double c[3];
 #pragma unroll
-        for (int i = 0; i < 3; i++) c[i] = (double)fa.cI[i * F + f];
+        for (int i = 0; i < 3; i++) c[i] = (double)fa.geo[quad_index<R>(F, f, i)];
         if (aJ == a)
 #pragma unroll
             for (int i = 0; i < 3; i++) c[i] -= len * n[i];
-        const double w = (double)fa.area[f] / len * E0;
+        const double w = (double)fa.geo[quad_index<R>(F, f, 3)] / len * E0;
         // columns of G: -e_j for the translations, c x e_j for the rotations
         double g[6][3];
 #pragma unroll

@@ -116,7 +116,7 @@ struct ldpm_system {
     int64_t* prog_off;
     double *prog_t, *prog_v, *progv, *red;
     double* mblk = nullptr;  // full cell mass blocks [N][72] (M rows, then G rows), or none
-    void *cI, *area, *frame, *ht, *hemax, *contrib;
+    void *geo, *frame, *hist, *contrib;  // geo, hist: quad layout (quad_index)
     int64_t n_prog_pts = 0, n_prog = 0;
     MatDev<double> matd;
     MatDev<float> matf;
@@ -136,11 +136,36 @@ struct ldpm_system {
     void* im_mem = nullptr;
     double *im_q, *im_qn, *im_vn, *im_an, *im_gn, *im_fn, *im_f1, *im_vp, *im_g, *im_R, *im_M, *im_binv;
     double *cg_x, *cg_r, *cg_z, *cg_p, *cg_Ap, *cg_sc, *cg_part, *im_red;
-    double *im_node_p, *im_ht_scr, *im_wint_scr, *im_con_scr, *im_ht_c, *im_hem_c, *im_wint_c;
+    double *im_node_p, *im_ht_scr, *im_wint_scr, *im_con_scr, *im_ht_c, *im_wint_c;  // histories: quads
     int cg_prev_its = 0;  // iterations of the last CG solve (schedules the host's convergence checks)
 };
 
 namespace {
+
+// [3][F] values and one [F] value (NULL: zeros) in the quad layout of the
+// given precision (quad_index), as doubles before the conversion to R
+std::vector<double> to_quads(const double* v3, const double* v1, int64_t F, int prec)
+{
+    std::vector<double> q(4 * (size_t)F);
+    const bool f32 = prec == LDPM_PREC_MIXED;
+    for (int64_t f = 0; f < F; f++)
+        for (int j = 0; j < 4; j++)
+            q[f32 ? quad_index<float>(F, f, j) : quad_index<double>(F, f, j)] =
+                j < 3 ? (v3 ? v3[j * F + f] : 0.0) : (v1 ? v1[f] : 0.0);
+    return q;
+}
+
+// the inverse: quads -> [3][F] and [F] (either may be NULL)
+void from_quads(const std::vector<double>& q, double* v3, double* v1, int64_t F, int prec)
+{
+    const bool f32 = prec == LDPM_PREC_MIXED;
+    for (int64_t f = 0; f < F; f++)
+        for (int j = 0; j < 4; j++) {
+            const double v = q[f32 ? quad_index<float>(F, f, j) : quad_index<double>(F, f, j)];
+            if (j < 3 && v3) v3[j * F + f] = v;
+            if (j == 3 && v1) v1[f] = v;
+        }
+}
 
 struct Carve {
     size_t off = 0;
@@ -283,8 +308,7 @@ template <typename R, int LAW, int TB, int MODE>
 static void launch_facet_m(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
 {
     NodeArgs na{s->tet, s->node, s->N, s->T};
-    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->frame, (R*)s->ht, (R*)s->hemax,
-                    s->F, s->E};
+    FacetArgs<R> fa{(const R*)s->geo, s->rec, (const R*)s->frame, (R*)s->hist, s->F, s->E};
     ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
     const MatDev<R>& mat = *(const MatDev<R>*)(sizeof(R) == 8 ? (const void*)&s->matd : (const void*)&s->matf);
     const int64_t nb = (s->T + TB - 1) / TB;
@@ -398,8 +422,7 @@ static hipError_t launch_persist_t(ldpm_system* s, int64_t nsteps)
     int64_t G = (int64_t)per_cu * s->n_cu;
     G = std::min<int64_t>(G, std::max<int64_t>(nb, np));
     NodeArgs na{s->tet, s->node, s->N, s->T};
-    FacetArgs<R> fa{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->frame, (R*)s->ht, (R*)s->hemax,
-                    s->F, s->E};
+    FacetArgs<R> fa{(const R*)s->geo, s->rec, (const R*)s->frame, (R*)s->hist, s->F, s->E};
     ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, s->n_prog};
     ParticleArgs pa{s->node, s->mass, s->inertia, s->mode, s->prog, s->scale, s->body,
                     s->fext, s->wext, s->wkin, s->ptr,     s->progv, s->flag, s->N, s->mblk};
@@ -655,15 +678,11 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     const size_t o_mblk = mblk.empty() ? 0 : cv.take<double>(72 * N);
     const size_t o_progv = cv.take<double>(2 * nP + 2);
     cv.off = (cv.off + 255) & ~size_t(255);
-    const size_t o_cI = cv.off; cv.off += 3 * F * rb;
-    cv.off = (cv.off + 255) & ~size_t(255);
-    const size_t o_area = cv.off; cv.off += F * rb;
+    const size_t o_geo = cv.off; cv.off += 4 * F * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
     const size_t o_frame = cv.off; cv.off += 8 * E * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
-    const size_t o_ht = cv.off; cv.off += 3 * F * rb;
-    cv.off = (cv.off + 255) & ~size_t(255);
-    const size_t o_hem = cv.off; cv.off += F * rb;
+    const size_t o_hist = cv.off; cv.off += 4 * F * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
     const size_t o_con = cv.off; cv.off += 4 * T * 6 * rb;
     cv.off = (cv.off + 255) & ~size_t(255);
@@ -703,8 +722,8 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->red = (double*)(B + o_red);
     s->mblk = mblk.empty() ? nullptr : (double*)(B + o_mblk);
     s->progv = (double*)(B + o_progv);
-    s->cI = B + o_cI; s->area = B + o_area; s->frame = B + o_frame;
-    s->ht = B + o_ht; s->hemax = B + o_hem; s->contrib = B + o_con;
+    s->geo = B + o_geo; s->frame = B + o_frame;
+    s->hist = B + o_hist; s->contrib = B + o_con;
 
     auto H2D = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         if (bytes == 0) return hipSuccess;
@@ -754,8 +773,10 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
         CK(H2D(s->prog_t, d->prog_t, npts * 8));
         CK(H2D(s->prog_v, d->prog_v, npts * 8));
     }
-    CK(put_r(s->cI, d->facet_cI, 3 * F));
-    CK(put_r(s->area, d->facet_area, F));
+    {
+        const std::vector<double> q = to_quads(d->facet_cI, d->facet_area, F, prec);
+        CK(put_r(s->geo, q.data(), 4 * F));
+    }
     std::vector<double> frec((size_t)8 * E, 0.0);
     for (int64_t r = 0; r < E; r++) {
         for (int c = 0; c < 3; c++) {
@@ -767,9 +788,10 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     }
     CK(put_r(s->frame, frec.data(), 8 * E));
     // history, accumulators
-    std::vector<double> zF(3 * F, 0.0);
-    CK(put_r(s->ht, (is && is->t) ? is->t : zF.data(), 3 * F));
-    CK(put_r(s->hemax, (is && is->emax) ? is->emax : zF.data(), F));
+    {
+        const std::vector<double> q = to_quads(is ? is->t : nullptr, is ? is->emax : nullptr, F, prec);
+        CK(put_r(s->hist, q.data(), 4 * F));
+    }
     CK(H2D(s->fext, (is && is->fext) ? is->fext : zeros6.data(), 6 * N * 8));
     CK(H2D(s->wext, (is && is->w_ext) ? is->w_ext : zeros6.data(), N * 8));
     CK(H2D(s->wkin, (is && is->w_kin) ? is->w_kin : zeros6.data(), N * 8));
@@ -898,8 +920,11 @@ ldpm_status ldpm_read_state(ldpm_system* s, ldpm_state* o)
         }
         return hipMemcpy(dst, src, n * 8, hipMemcpyDeviceToHost);
     };
-    if (o->t) HIP_TRY(get_r(o->t, s->ht, 3 * F));
-    if (o->emax) HIP_TRY(get_r(o->emax, s->hemax, F));
+    if (o->t || o->emax) {
+        std::vector<double> q(4 * (size_t)F);
+        HIP_TRY(get_r(q.data(), s->hist, 4 * F));
+        from_quads(q, o->t, o->emax, F, s->prec);
+    }
     o->step = s->step;
     return st;
 }
@@ -970,12 +995,12 @@ ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
     o->law = s->law;
     const double N = (double)s->N, T = (double)s->T, F = (double)s->F, E = (double)s->E;
     // facet kernel: each array touched once per launch
-    //   facets: rec 4 B + cI 3R + area R + history (t 3R + e_max R) read and written
+    //   facets: rec 4 B + geometry quad (c^I 3R, area R) + history quad (t 3R,
+    //   e_max R) read and written
     //   edge frames 8R per frame (n, m, l, 1/l); tets: nodes 16 B, pos 16 B,
     //   w_int 16 B (r+w), contributions written 24R; particles: x0, q, v read
     //   (15 doubles)
-    const double hist = (s->law == 1 ? 4.0 : 3.0) * rb;
-    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + 2.0 * hist) + E * 8.0 * rb + T * (16.0 + 16.0 + 16.0 + 24.0 * rb) +
+    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + 2.0 * 4.0 * rb) + E * 8.0 * rb + T * (16.0 + 16.0 + 16.0 + 24.0 * rb) +
                             N * 15.0 * 8.0;  // nodes: 15 of 16 words used
     // particle kernel: contributions 24R per tet read; per particle ptr 4 B,
     //   q, v, fext read + written (3 x 6 x 16 B), mass + inertia 32 B, scale 48 B,
@@ -1036,7 +1061,7 @@ std::vector<Region> dynamic_regions(ldpm_system* s)
     const size_t rb = rbytes(s->prec);
     const size_t N = (size_t)s->N, T = (size_t)s->T, F = (size_t)s->F;
     return {{s->node, 16 * N * 8}, {s->fext, 6 * N * 8}, {s->wext, N * 8},
-            {s->wkin, N * 8},  {s->wint, T * 8},    {s->ht, 3 * F * rb},  {s->hemax, F * rb}};
+            {s->wkin, N * 8},  {s->wint, T * 8},    {s->hist, 4 * F * rb}};
 }
 }  // namespace
 }  // extern "C++"
@@ -1294,8 +1319,7 @@ unsigned blocks_for(int64_t n, int th) { return (unsigned)((n + th - 1) / th); }
 template <typename R>
 FacetArgs<R> facet_args(ldpm_system* s)
 {
-    return FacetArgs<R>{(const R*)s->cI, (const R*)s->area, s->rec, (const R*)s->frame, (R*)s->ht, (R*)s->hemax,
-                        s->F, s->E};
+    return FacetArgs<R>{(const R*)s->geo, s->rec, (const R*)s->frame, (R*)s->hist, s->F, s->E};
 }
 }  // namespace
 }  // extern "C++"
@@ -1573,12 +1597,11 @@ hipError_t im_alloc(ldpm_system* s)
     o[k++] = cv.take<double>(3 * (size_t)IM_MAX_BLOCKS);            // cg_part (partials)
     o[k++] = cv.take<double>(8);                                    // im_red
     o[k++] = cv.take<double>(16 * N);                               // node_p
-    o[k++] = cv.take<double>(3 * F);                                // ht scratch
+    o[k++] = cv.take<double>(4 * F);                                // history scratch (quads)
     o[k++] = cv.take<double>(T);                                    // wint scratch
     o[k++] = cv.take<double>(24 * T);                               // contrib scratch
-    o[k++] = cv.take<double>(3 * F);                                // committed history copies
-    o[k++] = cv.take<double>(F);
-    o[k++] = cv.take<double>(T);
+    o[k++] = cv.take<double>(4 * F);                                // committed history (quads)
+    o[k++] = cv.take<double>(T);                                    // committed w_int
     const size_t bytes = (cv.off + 255) & ~size_t(255);
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, bytes);
@@ -1599,7 +1622,6 @@ hipError_t im_alloc(ldpm_system* s)
     s->im_wint_scr = (double*)(B + o[k++]);
     s->im_con_scr = (double*)(B + o[k++]);
     s->im_ht_c = (double*)(B + o[k++]);
-    s->im_hem_c = (double*)(B + o[k++]);
     s->im_wint_c = (double*)(B + o[k++]);
     return hipSuccess;
 }
@@ -1614,9 +1636,7 @@ hipError_t im_trial(ldpm_system* s, const double* q, int first)
     const int64_t N = s->N, T = s->T, F = s->F;
     hipLaunchKernelGGL(k_im_nodes, dim3(blocks_for(6 * N, 256)), dim3(256), 0, s->stream, s->node, q,
                        (const double*)s->im_qn, N);
-    hipError_t e = hipMemcpyAsync(s->ht, s->im_ht_c, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream);
-    if (e == hipSuccess && s->law != 0)
-        e = hipMemcpyAsync(s->hemax, s->im_hem_c, F * 8, hipMemcpyDeviceToDevice, s->stream);
+    hipError_t e = hipMemcpyAsync(s->hist, s->im_ht_c, 4 * F * 8, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->wint, s->im_wint_c, T * 8, hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return e;
     NodeArgs na{s->tet, s->node, N, T};
@@ -1635,8 +1655,7 @@ void im_k0_facets(ldpm_system* s)
 {
     NodeArgs na{s->tet, s->im_node_p, s->N, s->T};
     FacetArgs<double> fa = facet_args<double>(s);
-    fa.ht = s->im_ht_scr;
-    fa.hemax = nullptr;
+    fa.hist = s->im_ht_scr;
     const ProgArgs pr{s->prog_off, s->prog_t, s->prog_v, s->progv, 0};
     launch_facet_plain_l<0>(s, na, fa, s->im_con_scr, s->im_wint_scr, pr, 1, 1.0);
 }
@@ -1769,10 +1788,9 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
         HIP_TRY(hipMemcpyAsync(s->im_node_p, s->node, 16 * N * 8, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipMemsetAsync(s->cg_Ap, 0, n6 * 8, s->stream));
         hipLaunchKernelGGL(k_im_nodes, dim3(b6), dim3(256), 0, s->stream, s->im_node_p, (const double*)s->cg_Ap, nullptr, N);
-        HIP_TRY(hipMemsetAsync(s->im_ht_scr, 0, 3 * F * 8, s->stream));
+        HIP_TRY(hipMemsetAsync(s->im_ht_scr, 0, 4 * F * 8, s->stream));
         HIP_TRY(hipMemsetAsync(s->im_wint_scr, 0, T * 8, s->stream));
-        HIP_TRY(hipMemcpyAsync(s->im_ht_c, s->ht, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream));
-        if (s->law != 0) HIP_TRY(hipMemcpyAsync(s->im_hem_c, s->hemax, F * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->im_ht_c, s->hist, 4 * F * 8, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipMemcpyAsync(s->im_wint_c, s->wint, T * 8, hipMemcpyDeviceToDevice, s->stream));
         // a_0 from M a_0 = g(q_0) + f(0) on the free DoFs
         e = im_trial(s, s->im_qn, s->step == 0);
@@ -1785,8 +1803,7 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
                            s->im_gn, s->fext);
         HIP_TRY(hipGetLastError());
         // the trial left its history in place: back to the committed one
-        HIP_TRY(hipMemcpyAsync(s->ht, s->im_ht_c, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream));
-        if (s->law != 0) HIP_TRY(hipMemcpyAsync(s->hemax, s->im_hem_c, F * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->hist, s->im_ht_c, 4 * F * 8, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipMemcpyAsync(s->wint, s->im_wint_c, T * 8, hipMemcpyDeviceToDevice, s->stream));
         hipLaunchKernelGGL(k_im_pack, dim3(b6), dim3(256), 0, s->stream, s->node, (const double*)s->im_qn,
                            (const double*)s->im_vn, N);
@@ -1827,8 +1844,7 @@ ldpm_status ldpm_implicit_step(ldpm_system* s, const ldpm_implicit_opts* o, int6
         hipLaunchKernelGGL(k_im_accept, dim3(blocks_for(N, 256)), dim3(256), 0, s->stream, ia, (const double*)s->im_q,
                            (const double*)s->im_g, s->fext, s->wext, s->wkin, s->node, s->im_qn, s->im_vn, s->im_an,
                            s->im_gn, s->im_fn, s->flag);
-        HIP_TRY(hipMemcpyAsync(s->im_ht_c, s->ht, 3 * F * 8, hipMemcpyDeviceToDevice, s->stream));
-        if (s->law != 0) HIP_TRY(hipMemcpyAsync(s->im_hem_c, s->hemax, F * 8, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->im_ht_c, s->hist, 4 * F * 8, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipMemcpyAsync(s->im_wint_c, s->wint, T * 8, hipMemcpyDeviceToDevice, s->stream));
         HIP_TRY(hipGetLastError());
         s->step++;

@@ -12,14 +12,23 @@
 // ---------------------------------------------------------------------------
 // device argument blocks
 // ---------------------------------------------------------------------------
+// Four values of a facet in 16-byte chunks: [QC][F][QK], QK = 16 / sizeof(R)
+// values per chunk and QC = 4 / QK chunks, so that one lane moves a facet's
+// record with one (FP32) or two (FP64) 16-byte accesses.
+template <typename R>
+constexpr int QK = 16 / (int)sizeof(R);
+template <typename R>
+__host__ __device__ __forceinline__ int64_t quad_index(int64_t F, int64_t f, int j)
+{
+    return ((int64_t)(j / QK<R>) * F + f) * QK<R> + j % QK<R>;
+}
+
 template <typename R>
 struct FacetArgs {
-    const R* __restrict__ cI;      // [3][F]
-    const R* __restrict__ area;    // [F]
+    const R* __restrict__ geo;     // quads c^I[3], area
     const int32_t* __restrict__ rec;  // [F]
-    const R* __restrict__ frame;   // [E][8]: n[3], m[3], len, pad
-    R* __restrict__ ht;            // [3][F]
-    R* __restrict__ hemax;         // [F]
+    const R* __restrict__ frame;   // [E][8]: n[3], m[3], len, 1/len
+    R* __restrict__ hist;          // quads t_N, t_M, t_L, e_max
     int64_t F, E;
 };
 
@@ -127,6 +136,32 @@ template <typename T>
 __device__ __forceinline__ void st_once(T v, T* p)
 {
     __builtin_nontemporal_store(v, p);
+}
+
+typedef double quad_d2 __attribute__((ext_vector_type(2)));
+typedef float quad_f4 __attribute__((ext_vector_type(4)));
+
+// the four values of facet f (quad layout), loaded / stored once
+template <typename R>
+__device__ __forceinline__ void ld_quad(const R* base, int64_t F, int64_t f, R& a, R& b, R& c, R& e)
+{
+    if constexpr (sizeof(R) == 8) {
+        const quad_d2 x = ld_once((const quad_d2*)base + f), y = ld_once((const quad_d2*)base + F + f);
+        a = x.x; b = x.y; c = y.x; e = y.y;
+    } else {
+        const quad_f4 x = ld_once((const quad_f4*)base + f);
+        a = x.x; b = x.y; c = x.z; e = x.w;
+    }
+}
+template <typename R>
+__device__ __forceinline__ void st_quad(R* base, int64_t F, int64_t f, R a, R b, R c, R e)
+{
+    if constexpr (sizeof(R) == 8) {
+        st_once(quad_d2{a, b}, (quad_d2*)base + f);
+        st_once(quad_d2{c, e}, (quad_d2*)base + F + f);
+    } else {
+        st_once(quad_f4{a, b, c, e}, (quad_f4*)base + f);
+    }
 }
 
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap)
@@ -275,10 +310,8 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
         m0 = fr[3]; m1 = fr[4]; m2 = fr[5];
         len = fr[6];
         ilen = fr[7];
-        cI0 = ld_once(&fa.cI[f]); cI1 = ld_once(&fa.cI[F + f]); cI2 = ld_once(&fa.cI[2 * F + f]);
-        A = ld_once(&fa.area[f]);
-        tv[0] = ld_once(&fa.ht[f]); tv[1] = ld_once(&fa.ht[F + f]); tv[2] = ld_once(&fa.ht[2 * F + f]);
-        if (LAW != 0) emx = ld_once(&fa.hemax[f]);
+        ld_quad(fa.geo, F, f, cI0, cI1, cI2, A);
+        ld_quad((const R*)fa.hist, F, f, tv[0], tv[1], tv[2], emx);
     }
     // output position (incidence order) of the tet-node sums of phase D, and
     // the tet's accumulated internal work
@@ -403,6 +436,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
             eV = (R)((s_ev[tl] + s_ev[TB + tl] + s_ev[2 * TB + tl] + s_ev[3 * TB + tl]) / 3.0);
         }
         bool exact = fvalid;
+        const R emx0 = emx;  // e_max before this step (capture gate)
         if constexpr (MODE == MODE_SURROGATE) {
             // gate: in-envelope facets not yet handed back go through the MLP
             uint8_t fl = 1;
@@ -484,7 +518,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
         }
         if constexpr (MODE == MODE_CAPTURE) {
             if (fvalid && (f % cp.fstride) == cp.foff && (step % cp.sstride) == 0 &&
-                in_envelope(mat, e, eV, told, (R)fa.hemax[f], cp.gate) &&
+                in_envelope(mat, e, eV, told, emx0, cp.gate) &&
                 facet_damage(mat, e, tv) <= cp.gate.damage_max) {
                 float x[MLP_IN];
                 const AlignedFrame fr = surrogate_features(mat, e, de, told, x);
@@ -510,10 +544,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
             }
         }
         if (fvalid) {
-            st_once(tv[0], &fa.ht[f]);
-            st_once(tv[1], &fa.ht[F + f]);
-            st_once(tv[2], &fa.ht[2 * F + f]);
-            if (LAW != 0) st_once(emx, &fa.hemax[f]);
+            st_quad(fa.hist, F, f, tv[0], tv[1], tv[2], emx);
             // internal work A l (t_old + t)/2 . de
             wk = (double)(A * len * R(0.5) *
                           ((told[0] + tv[0]) * de[0] + (told[1] + tv[1]) * de[1] + (told[2] + tv[2]) * de[2]));
