@@ -1,7 +1,8 @@
 // Small MLP (9 -> 64 -> 64 -> 64 -> 3, tanh) on CDNA4 matrix cores:
 // BF16 operands, FP32 accumulation, v_mfma_f32_16x16x32_bf16 tiles, one
-// wave per 64 rows.  Shared by the surrogate facet kernel (inference) and
-// the training kernels.
+// wave per 64 rows.  Inference (the surrogate facet kernel and
+// k_mlp_forward) keeps the activations in registers (mlp_infer_wave); the
+// training kernels stage them in LDS (wave_gemm64, MlpBf16).
 //
 // Parameters (flat FP32 vector, 9155 values, weights stored [out][in]):
 //   W1[64][9] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]
@@ -84,31 +85,6 @@ __device__ __forceinline__ void wave_gemm64(const __bf16* __restrict__ A, int pa
     }
 }
 
-// Forward pass of one wave's 64 rows, in place: buf holds the input rows
-// (64 x PA pitch, first 32 columns = padded features) and receives each
-// layer's activations; out[m*4 + j] receives the 3 outputs of row m.
-// Every A fragment of an M tile is read into registers before that tile's
-// rows are overwritten, and a wave's LDS accesses complete in order.
-__device__ __forceinline__ void mlp_forward_wave(const MlpBf16& W, __bf16* buf, float* out)
-{
-    wave_gemm64<1, 4>(buf, PA, W.w1, PA1, [&](int m, int n, float v) {
-        buf[m * PA + n] = to_bf16(act_tanh(v + W.b1[n]));
-    });
-    __builtin_amdgcn_wave_barrier();
-    wave_gemm64<2, 4>(buf, PA, W.w2, PA, [&](int m, int n, float v) {
-        buf[m * PA + n] = to_bf16(act_tanh(v + W.b2[n]));
-    });
-    __builtin_amdgcn_wave_barrier();
-    wave_gemm64<2, 4>(buf, PA, W.w3, PA, [&](int m, int n, float v) {
-        buf[m * PA + n] = to_bf16(act_tanh(v + W.b3[n]));
-    });
-    __builtin_amdgcn_wave_barrier();
-    wave_gemm64<2, 1>(buf, PA, W.w4, PA, [&](int m, int n, float v) {
-        if (n < MLP_OUT) out[m * 4 + n] = v + W.b4[n];
-    });
-    __builtin_amdgcn_wave_barrier();
-}
-
 // Fill an MlpBf16 (LDS or global) from the flat FP32 parameters, block-wide.
 __device__ __forceinline__ void mlp_load_bf16(const float* __restrict__ p, MlpBf16& W, int tid, int nth)
 {
@@ -131,6 +107,182 @@ __device__ __forceinline__ void mlp_load_bf16(const float* __restrict__ p, MlpBf
         W.b3[i] = p[P_B3 + i];
     }
     for (int i = tid; i < N4; i += nth) W.b4[i] = i < MLP_OUT ? p[P_B4 + i] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Inference with the activations in registers.  Each layer is computed
+// transposed, D = W H^T (A operand: weight rows n, B operand: activation
+// rows m), so that after a layer lane (r, g) = (l % 16, l / 16) of a 16-row
+// tile holds the outputs n = 16 nt + 4 g + i (nt, i = 0..3) of row r: 16
+// values, which it passes on as the next layer's B operand.  The dot product
+// does not depend on which K slot carries which k (A and B share the
+// slots), so the next layer's K slots follow what the lane holds: slot j of
+// K step kt in lane group g carries k = 16 (2 kt + j / 4) + 4 g + j % 4.
+// The weights are stored in LDS with that assignment, fragment by fragment
+// ([tile][step][lane] of 8 values: one conflict-free 16-byte read per lane
+// and MFMA).  Layer 1 has one K step: lane group 0 carries features 0..7,
+// group 1 feature 8, groups 2 and 3 zeros.  The output layer uses rows 0..2
+// of one 16-row tile (rows 3..15 zero).  Rounding points are those of the
+// LDS-staged form: BF16 inputs, weights and activations, FP32 sums.
+// ---------------------------------------------------------------------------
+struct MlpFrag {
+    bf16x8 w1[4][64];     // [n tile][lane]
+    bf16x8 w2[4][2][64];  // [n tile][K step][lane]
+    bf16x8 w3[4][2][64];
+    bf16x8 w4[2][64];     // [K step][lane]
+    float b1[MLP_H], b2[MLP_H], b3[MLP_H], b4[N4];
+};
+
+// k carried by slot j of K step kt in lane group g (hidden layers)
+__host__ __device__ __forceinline__ int frag_k(int kt, int g, int j) { return (2 * kt + (j >> 2)) * 16 + 4 * g + (j & 3); }
+
+// Fill an MlpFrag (LDS) from the flat FP32 parameters, block-wide.
+__device__ __forceinline__ void mlp_load_frag(const float* __restrict__ p, MlpFrag& W, int tid, int nth)
+{
+    __bf16* w1 = (__bf16*)W.w1;
+    for (int i = tid; i < 4 * 64 * 8; i += nth) {
+        const int j = i & 7, lane = (i >> 3) & 63, nt = i >> 9;
+        const int n = nt * 16 + (lane & 15), g = lane >> 4;
+        const int k = g == 0 ? j : ((g == 1 && j == 0) ? 8 : -1);
+        w1[i] = to_bf16(k >= 0 ? p[P_W1 + n * MLP_IN + k] : 0.f);
+    }
+    __bf16 *w2 = (__bf16*)W.w2, *w3 = (__bf16*)W.w3;
+    for (int i = tid; i < 4 * 2 * 64 * 8; i += nth) {
+        const int j = i & 7, lane = (i >> 3) & 63, kt = (i >> 9) & 1, nt = i >> 10;
+        const int n = nt * 16 + (lane & 15), k = frag_k(kt, lane >> 4, j);
+        w2[i] = to_bf16(p[P_W2 + n * MLP_H + k]);
+        w3[i] = to_bf16(p[P_W3 + n * MLP_H + k]);
+    }
+    __bf16* w4 = (__bf16*)W.w4;
+    for (int i = tid; i < 2 * 64 * 8; i += nth) {
+        const int j = i & 7, lane = (i >> 3) & 63, kt = i >> 9;
+        const int n = lane & 15, k = frag_k(kt, lane >> 4, j);
+        w4[i] = to_bf16(n < MLP_OUT ? p[P_W4 + n * MLP_H + k] : 0.f);
+    }
+    for (int i = tid; i < MLP_H; i += nth) {
+        W.b1[i] = p[P_B1 + i];
+        W.b2[i] = p[P_B2 + i];
+        W.b3[i] = p[P_B3 + i];
+    }
+    for (int i = tid; i < N4; i += nth) W.b4[i] = i < MLP_OUT ? p[P_B4 + i] : 0.f;
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned pack_bf16(float a, float b)
+{
+    const bf16x2 v = {to_bf16(a), to_bf16(b)};
+    return __builtin_bit_cast(unsigned, v);
+}
+
+// tanh of the biased results of the four n tiles, packed as the next
+// layer's two K steps (tile 2 kt + t fills slots 4 t .. 4 t + 3 of step kt)
+__device__ __forceinline__ void act_pack(const f32x4 (&c)[4], const float* bias, int g, bf16x8 (&h)[2])
+{
+    u32x4 q[2];
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+        const float* b = bias + nt * 16 + 4 * g;
+        const unsigned lo = pack_bf16(act_tanh(c[nt][0] + b[0]), act_tanh(c[nt][1] + b[1]));
+        const unsigned hi = pack_bf16(act_tanh(c[nt][2] + b[2]), act_tanh(c[nt][3] + b[3]));
+        if (nt & 1) {
+            q[nt >> 1][2] = lo;
+            q[nt >> 1][3] = hi;
+        } else {
+            q[nt >> 1][0] = lo;
+            q[nt >> 1][1] = hi;
+        }
+    }
+    h[0] = __builtin_bit_cast(bf16x8, q[0]);
+    h[1] = __builtin_bit_cast(bf16x8, q[1]);
+}
+
+// one hidden layer on MT 16-row tiles: h (two K steps per tile) -> h; each
+// weight fragment read from LDS serves the MT tiles
+template <int MT>
+__device__ __forceinline__ void hidden_layer(const bf16x8 (&w)[4][2][64], const float* bias, int l,
+                                             bf16x8 (&h)[MT][2])
+{
+    f32x4 c[MT][4];
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+        const bf16x8 w0 = w[nt][0][l], w1 = w[nt][1][l];
+#pragma unroll
+        for (int t = 0; t < MT; t++) {
+            c[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, h[t][0], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            c[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, h[t][1], c[t][nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; t++) act_pack(c[t], bias, l >> 4, h[t]);
+}
+
+// Forward pass of one wave: lane l passes its row's (normalised) features
+// x and receives that row's outputs y.  Every lane of the wave must take
+// part (wave-uniform call).  The four 16-row tiles are taken MT at a time.
+template <int MT = 2>
+__device__ __forceinline__ void mlp_infer_wave(const MlpFrag& W, const float (&x)[MLP_IN], float (&y)[MLP_OUT])
+{
+    const int l = threadIdx.x & 63, g = l >> 4;
+    const int P0 = (int)pack_bf16(x[0], x[1]), P1 = (int)pack_bf16(x[2], x[3]);
+    const int P2 = (int)pack_bf16(x[4], x[5]), P3 = (int)pack_bf16(x[6], x[7]);
+    const int P4 = (int)pack_bf16(x[8], 0.f);
+#pragma unroll
+    for (int k = 0; k < MLP_OUT; k++) y[k] = 0.f;
+#pragma unroll 1
+    for (int m0 = 0; m0 < 4; m0 += MT) {
+        // the weight fragments are re-read from LDS for every group of row
+        // tiles rather than held in registers across groups (88 VGPRs)
+        __asm__ volatile("" ::: "memory");
+        bf16x8 h[MT][2];
+        {
+            // layer-1 operand: the features of row 16 mt + r, from that row's lane
+            bf16x8 xin[MT];
+#pragma unroll
+            for (int t = 0; t < MT; t++) {
+                const int src = ((m0 + t) * 16 + (l & 15)) * 4;
+                const unsigned q0 = (unsigned)__builtin_amdgcn_ds_bpermute(src, P0);
+                const unsigned q1 = (unsigned)__builtin_amdgcn_ds_bpermute(src, P1);
+                const unsigned q2 = (unsigned)__builtin_amdgcn_ds_bpermute(src, P2);
+                const unsigned q3 = (unsigned)__builtin_amdgcn_ds_bpermute(src, P3);
+                const unsigned q4 = (unsigned)__builtin_amdgcn_ds_bpermute(src, P4);
+                const u32x4 in = g == 0 ? u32x4{q0, q1, q2, q3} : (g == 1 ? u32x4{q4, 0u, 0u, 0u} : u32x4{0u, 0u, 0u, 0u});
+                xin[t] = __builtin_bit_cast(bf16x8, in);
+            }
+            f32x4 c[MT][4];
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) {
+                const bf16x8 w = W.w1[nt][l];
+#pragma unroll
+                for (int t = 0; t < MT; t++)
+                    c[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xin[t], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < MT; t++) act_pack(c[t], W.b1, g, h[t]);
+        }
+        hidden_layer<MT>(W.w2, W.b2, l, h);
+        hidden_layer<MT>(W.w3, W.b3, l, h);
+        f32x4 o[MT];
+        {
+            const bf16x8 w0 = W.w4[0][l], w1 = W.w4[1][l];
+#pragma unroll
+            for (int t = 0; t < MT; t++) {
+                o[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, h[t][0], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                o[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, h[t][1], o[t], 0, 0, 0);
+            }
+        }
+        // lane (r, 0) holds outputs 0..3 of row 16 mt + r; that row's lane takes them
+#pragma unroll
+        for (int t = 0; t < MT; t++) {
+#pragma unroll
+            for (int k = 0; k < MLP_OUT; k++) {
+                const float v = __builtin_bit_cast(
+                    float, __builtin_amdgcn_ds_bpermute((l & 15) * 4, __builtin_bit_cast(int, o[t][k] + W.b4[k])));
+                if ((l >> 4) == m0 + t) y[k] = v;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

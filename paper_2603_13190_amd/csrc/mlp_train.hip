@@ -210,18 +210,16 @@ __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __re
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ params, const float* __restrict__ X,
                                                      int64_t n, float* __restrict__ Y)
 {
-    __shared__ MlpBf16 W;
-    __shared__ __align__(16) __bf16 buf[4][64 * PA];
-    __shared__ float out[4][64 * 4];
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    mlp_load_bf16(params, W, tid, 256);
+    __shared__ MlpFrag W;
+    const int tid = threadIdx.x;
+    mlp_load_frag(params, W, tid, 256);
     const int64_t row = (int64_t)blockIdx.x * 256 + tid;
-    for (int k = 0; k < PA; k++) buf[w][l * PA + k] = to_bf16((k < MLP_IN && row < n) ? X[row * MLP_IN + k] : 0.f);
+    float x[MLP_IN], y[MLP_OUT];
+    for (int k = 0; k < MLP_IN; k++) x[k] = row < n ? X[row * MLP_IN + k] : 0.f;
     __syncthreads();
-    mlp_forward_wave(W, buf[w], out[w]);
-    __syncthreads();
+    mlp_infer_wave(W, x, y);
     if (row < n)
-        for (int j = 0; j < MLP_OUT; j++) Y[row * MLP_OUT + j] = out[w][l * 4 + j];
+        for (int j = 0; j < MLP_OUT; j++) Y[row * MLP_OUT + j] = y[j];
 }
 
 }  // namespace

@@ -243,17 +243,10 @@ __device__ __forceinline__ AlignedFrame surrogate_features(const MatDev<R>& p, c
     return fr;
 }
 
-// LDS of the surrogate: weights of the block plus one activation tile per wave
-template <int NW>
-struct MlpSmem {
-    MlpBf16 W;
-    __bf16 buf[NW][64 * PA];
-    float out[NW][64 * 4];
-};
-template <int NW>
-__device__ __forceinline__ MlpSmem<NW>& mlp_smem()
+// LDS of the surrogate: the block's copy of the network's weights
+__device__ __forceinline__ MlpFrag& mlp_smem()
 {
-    __shared__ MlpSmem<NW> sm;
+    __shared__ MlpFrag sm;
     return sm;
 }
 
@@ -458,24 +451,19 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
                 }
             }
             const bool use_nn = fvalid && !fl;
-            auto& sm = mlp_smem<NF / 64>();
-            const int w = tid >> 6, lane = tid & 63;
-            if (__any(use_nn)) {  // wave-uniform: the whole wave runs the tiles
-                __bf16* buf = sm.buf[w];
+            if (__any(use_nn)) {  // wave-uniform: the whole wave runs the network
+                float xin[MLP_IN], y[MLP_OUT];
 #pragma unroll
-                for (int k = 0; k < K1; k++)
-                    buf[lane * PA + k] =
-                        to_bf16((use_nn && k < MLP_IN) ? (x[k] - sg.xmean[k]) * sg.xscale[k] : 0.f);
-                __builtin_amdgcn_wave_barrier();
-                mlp_forward_wave(sm.W, buf, sm.out[w]);
+                for (int k = 0; k < MLP_IN; k++) xin[k] = use_nn ? (x[k] - sg.xmean[k]) * sg.xscale[k] : 0.f;
+                mlp_infer_wave(mlp_smem(), xin, y);
                 if (use_nn) {
                     // traction = elastic predictor + residual, the residual
                     // relative to s = |t_old + E de| + tau; below the
                     // network's error floor a relative residual is zero
                     const float s_tr = trial_norm(mat, told, de) + sg.ytau;
-                    float r0 = sm.out[w][lane * 4 + 0] * sg.yscale[0];
-                    float r1 = sm.out[w][lane * 4 + 1] * sg.yscale[1];
-                    float r2 = sm.out[w][lane * 4 + 2] * sg.yscale[2];
+                    float r0 = y[0] * sg.yscale[0];
+                    float r1 = y[1] * sg.yscale[1];
+                    float r2 = y[2] * sg.yscale[2];
                     r0 = (fabsf(r0) < sg.ydead[0] ? 0.f : r0) * s_tr;
                     r1 = (fabsf(r1) < sg.ydead[1] ? 0.f : r1) * s_tr;
                     r2 = (fabsf(r2) < sg.ydead[2] ? 0.f : r2) * s_tr;
@@ -613,21 +601,23 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
                                                    ProgArgs pr, int64_t step, double dt, int remap,
                                                    SurrogateArgs sg, CaptureArgs cp)
 {
-    if constexpr (MODE == MODE_SURROGATE) mlp_load_bf16(sg.params, mlp_smem<12 * TB / 64>().W, threadIdx.x, 12 * TB);
+    if constexpr (MODE == MODE_SURROGATE) mlp_load_frag(sg.params, mlp_smem(), threadIdx.x, 12 * TB);
     facet_tile<R, LAW, TB, MODE>(xcd_block(blockIdx.x, gridDim.x, remap), blockIdx.x == 0, na, fa, mat, pos,
                                  contrib, wint, pr, step, dt, sg, cp);
 }
 
 // Grid-stride loop over tiles: blocks stay resident and load the surrogate's
-// weights into LDS once instead of once per tile.
+// weights into LDS once instead of once per tile.  At least 3 waves per SIMD
+// (at most 168 VGPRs): four 16-tet blocks per CU, as many as their LDS
+// (weights and tile) allows.
 template <typename R, int LAW, int TB, int MODE>
-__global__ __launch_bounds__(12 * TB) void k_facet_loop(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
+__global__ __launch_bounds__(12 * TB, 3) void k_facet_loop(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
                                                         const int32_t* __restrict__ pos,
                                                         R* __restrict__ contrib, double* __restrict__ wint,
                                                         ProgArgs pr, int64_t step, double dt,
                                                         SurrogateArgs sg, CaptureArgs cp)
 {
-    if constexpr (MODE == MODE_SURROGATE) mlp_load_bf16(sg.params, mlp_smem<12 * TB / 64>().W, threadIdx.x, 12 * TB);
+    if constexpr (MODE == MODE_SURROGATE) mlp_load_frag(sg.params, mlp_smem(), threadIdx.x, 12 * TB);
     const int64_t nb = (na.T + TB - 1) / TB;
     SgCount c;
     for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x)
