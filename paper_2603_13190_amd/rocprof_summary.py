@@ -1,9 +1,15 @@
 """Summarise rocprofv3 output into the short text/JSON records kept in profiles/.
 
-  python -m paper_2603_13190_amd.rocprof_summary stats  <kernel_stats.csv> <out.txt> <command...>
+  python -m paper_2603_13190_amd.rocprof_summary stats  <kernel_stats.csv> <out.txt>
+         [--tail "<kernel name>=N"]... <command...>
   python -m paper_2603_13190_amd.rocprof_summary pmc    <fetch_counter_collection.csv>
          <write_counter_collection.csv> <out.json> <calibration_bytes> <command...>
   python -m paper_2603_13190_amd.rocprof_summary counters <counter_collection.csv> <out.txt> <command...>
+
+--tail adds, from the per-dispatch trace next to the stats file
+(*_kernel_trace.csv), the average duration of the kernel's last N
+dispatches: the steps a benchmark profiles at the end of a run, whose
+average it reports from HIP events.
 
 The PMC mode reads FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the facet
 kernels and of the calibration copy kernel (a plain device-to-device copy of
@@ -45,7 +51,16 @@ def _short(name):
     return name[:90]
 
 
-def stats(csv_path, out_path, command):
+def tail_average(trace_csv, kernel, n):
+    """Average duration (us) and count of the last n dispatches of kernel
+    (by start time) in a rocprofv3 kernel trace."""
+    d = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in _rows(trace_csv)
+               if _short(r["Kernel_Name"]) == kernel)
+    d = d[-n:]
+    return (sum(e - b for b, e in d) / len(d) / 1e3 if d else None), len(d)
+
+
+def stats(csv_path, out_path, command, tails=()):
     rows = _rows(csv_path)
     lines = [f"command: {command}", f"source: {os.path.basename(csv_path)} (rocprofv3 --kernel-trace --stats)",
              f"kernel sources sha1: {source_sha1()}", "",
@@ -59,6 +74,12 @@ def stats(csv_path, out_path, command):
         tot = float(r.get("TotalDurationNs", 0)) / 1e6
         pct = float(r.get("Percentage", 0))
         lines.append(f"{_short(name):60s} {calls:8d} {avg:10.2f} {mn:10.2f} {mx:10.2f} {tot:10.2f} {pct:6.2f}")
+    if tails:
+        trace = csv_path.replace("kernel_stats", "kernel_trace")
+        lines.append("")
+        for kernel, n in tails:
+            avg, cnt = tail_average(trace, kernel, n)
+            lines.append(f"last {cnt} dispatches of {kernel}: avg {avg:.2f} us ({os.path.basename(trace)})")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -138,7 +159,12 @@ def counters(csv_path, out_path, command):
 if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "stats":
-        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        rest, tails = sys.argv[4:], []
+        while rest and rest[0] == "--tail":
+            k, n = rest[1].rsplit("=", 1)
+            tails.append((k, int(n)))
+            rest = rest[2:]
+        stats(sys.argv[2], sys.argv[3], " ".join(rest), tails)
     elif mode == "pmc":
         pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], " ".join(sys.argv[6:]))
     elif mode == "counters":
