@@ -99,6 +99,13 @@ def timed_run(sysd, precision, warmup, steps, launch=None, tune=None):
     return g, ms, wall
 
 
+def facet_kernel_name(precision, launch):
+    """The two-kernel step's facet kernel as profilers name it (template
+    arguments: precision, law, tets per block, mode, nontemporal streams)."""
+    return (f"k_facet<{'double' if precision == 'fp64' else 'float'}, 1, {launch['tets_per_block']}, 0, "
+            f"{launch['stream_facets']}>")
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None when the kernel sources changed since the counters were taken."""
@@ -656,7 +663,7 @@ def window_case(sysd, workload, runs, warmup, steps, tune, field=None, key=None)
                      facet_kernel_GBs=info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9,
                      facet_kernel_frac_hbm=info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9 / PEAK_HBM_GBS)
             if prec == "fp64" and key:
-                kname = "k_facet<double, 1, %d, 0>" % g.get_launch()["tets_per_block"]
+                kname = facet_kernel_name("fp64", g.get_launch())
                 r["facet_kernel_alg_bytes"] = info["facet_kernel_bytes"]
                 r["facet_kernel_traffic"] = measured_traffic(key, kname)
         else:
@@ -737,8 +744,7 @@ def window_run(sysd, precision, start, warmup, steps, tune, profile_steps, key=N
         fms, pms = g.step_profiled(profile_steps)
         favg, pavg = fms / profile_steps, pms / profile_steps
         bts = info["facet_kernel_bytes"]
-        r.update(facet_kernel=f"k_facet<{'double' if precision == 'fp64' else 'float'}, 1, "
-                              f"{launch['tets_per_block']}, 0>",
+        r.update(facet_kernel=facet_kernel_name(precision, launch),
                  facet_kernel_avg_us=favg * 1e3, particle_kernel_avg_us=pavg * 1e3,
                  facet_kernel_bytes=bts, particle_kernel_bytes=info["particle_kernel_bytes"],
                  facet_kernel_GBs=bts / (favg * 1e-3) / 1e9,

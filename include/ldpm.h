@@ -223,20 +223,27 @@ ldpm_status ldpm_get_info(ldpm_system *s, ldpm_info *out);
  * facet kernel's tiles are remapped so that each XCD (own L2) works on a
  * contiguous range, and whether ldpm_step runs as one persistent
  * cooperative launch per chunk of steps (facet and particle phases separated
- * by grid barriers) instead of two kernels per step (lumped mass only).
- * Results do not depend on it (bitwise).                                    */
+ * by grid barriers) instead of two kernels per step (lumped mass only), and
+ * whether the two-kernel step's facet kernel streams the facet records and
+ * traction history past the caches (nontemporal loads and stores: what the step reuses stays
+ * cached when its data exceed the last-level cache) or through them (the
+ * whole step can stay cache-resident on smaller systems).  stream_facets
+ * defaults to 1 when the facet kernel moves more than 256 MiB per launch,
+ * else 0.  Results do not depend on any of these (bitwise).               */
 typedef struct {
     int32_t tets_per_block;
     int32_t particle_threads;
     int32_t xcd_remap;
     int32_t persistent;
+    int32_t stream_facets;
 } ldpm_launch;
 ldpm_status ldpm_set_launch(ldpm_system *s, const ldpm_launch *cfg);
 ldpm_status ldpm_get_launch(ldpm_system *s, ldpm_launch *out);
 
 /* Autotuner: times every launch shape (tets_per_block x particle_threads x
  * xcd_remap for two kernels per step, and tets_per_block for the persistent
- * launch) for steps_per_trial steps on the live system, keeps the
+ * launch, at the handle's stream_facets; then the best two-kernel shape
+ * with stream_facets flipped) for steps_per_trial steps on the live system, keeps the
  * fastest and returns it (best, best_us = microseconds per step).  The
  * dynamic state is saved before the trials and restored afterwards (a
  * temporary device buffer of the state's size is allocated), so the

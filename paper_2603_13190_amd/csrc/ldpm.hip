@@ -106,7 +106,7 @@ struct ldpm_system {
     void* (*dev_alloc)(size_t, void*) = nullptr;
     void* alloc_ctx = nullptr;
     int device = 0;
-    ldpm_launch launch{16, 256, 1, 0};
+    ldpm_launch launch{16, 256, 1, 0, 0};
     int n_cu = 0;
     // device pointers
     double *node, *mass, *inertia, *scale, *body, *fext, *wext, *wkin, *wint;
@@ -166,6 +166,21 @@ void from_quads(const std::vector<double>& q, double* v3, double* v1, int64_t F,
             if (j == 3 && v1) v1[f] = v;
         }
 }
+
+// bytes the facet kernel moves per launch, each array touched once:
+//   facets: rec 4 B + geometry quad (c^I 3R, area R) + history quad (t 3R,
+//   e_max R) read and written; edge frames 8R per frame (n, m, l, 1/l);
+//   tets: nodes 16 B, pos 16 B, w_int 16 B (r+w), contributions written 24R;
+//   particles: x0, q, v read (15 of the record's 16 doubles)
+double facet_kernel_bytes(int64_t N, int64_t T, int64_t F, int64_t E, size_t rb)
+{
+    return (double)F * (4.0 + 4.0 * rb + 2.0 * 4.0 * rb) + (double)E * 8.0 * rb +
+           (double)T * (16.0 + 16.0 + 16.0 + 24.0 * rb) + (double)N * 15.0 * 8.0;
+}
+
+// above this many bytes per launch the facet streams bypass the caches by
+// default (the MI355X's last-level Infinity Cache holds 256 MiB)
+constexpr double STREAM_FACETS_BYTES = 256.0 * 1024 * 1024;
 
 struct Carve {
     size_t off = 0;
@@ -326,12 +341,16 @@ static void launch_facet_m(ldpm_system* s, hipEvent_t ev0, hipEvent_t ev1)
                                s->cp);
         return;
     }
+    // the two-kernel step's facet streams: nontemporal (NT = 1) or cached
+    auto kern = k_facet<R, LAW, TB, MODE, 0>;
+    if constexpr (MODE == MODE_PLAIN)
+        if (s->launch.stream_facets) kern = k_facet<R, LAW, TB, MODE, 1>;
     if (ev0)
-        hipExtLaunchKernelGGL((k_facet<R, LAW, TB, MODE>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, ev0, ev1,
-                              0, na, fa, mat, (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt,
+        hipExtLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, ev0, ev1, 0, na, fa, mat,
+                              (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt,
                               s->launch.xcd_remap, s->sg, s->cp);
     else
-        hipLaunchKernelGGL((k_facet<R, LAW, TB, MODE>), dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(12 * TB), 0, s->stream, na, fa, mat,
                            (const int32_t*)s->pos, (R*)s->contrib, s->wint, pr, s->step, s->dt, s->launch.xcd_remap,
                            s->sg, s->cp);
 }
@@ -696,6 +715,7 @@ ldpm_status ldpm_load_system(const ldpm_system_desc* d, ldpm_system** out)
     s->dev_alloc = d->dev_alloc;
     s->alloc_ctx = d->alloc_ctx;
     s->n_prog = nP; s->n_prog_pts = npts;
+    s->launch.stream_facets = facet_kernel_bytes(N, T, F, E, rb) > STREAM_FACETS_BYTES ? 1 : 0;
     s->matd = make_mat<double>(mat);
     s->matf = make_mat<float>(mat);
     (void)hipGetDevice(&s->device);
@@ -994,14 +1014,7 @@ ldpm_status ldpm_get_info(ldpm_system* s, ldpm_info* o)
     o->precision = s->prec;
     o->law = s->law;
     const double N = (double)s->N, T = (double)s->T, F = (double)s->F, E = (double)s->E;
-    // facet kernel: each array touched once per launch
-    //   facets: rec 4 B + geometry quad (c^I 3R, area R) + history quad (t 3R,
-    //   e_max R) read and written
-    //   edge frames 8R per frame (n, m, l, 1/l); tets: nodes 16 B, pos 16 B,
-    //   w_int 16 B (r+w), contributions written 24R; particles: x0, q, v read
-    //   (15 doubles)
-    o->facet_kernel_bytes = F * (4.0 + 4.0 * rb + 2.0 * 4.0 * rb) + E * 8.0 * rb + T * (16.0 + 16.0 + 16.0 + 24.0 * rb) +
-                            N * 15.0 * 8.0;  // nodes: 15 of 16 words used
+    o->facet_kernel_bytes = facet_kernel_bytes(s->N, s->T, s->F, s->E, (size_t)rb);
     // particle kernel: contributions 24R per tet read; per particle ptr 4 B,
     //   q, v, fext read + written (3 x 6 x 16 B), mass + inertia 32 B, scale 48 B,
     //   prog 24 B, mode 6 B, w_ext r+w 16 B, w_kin 8 B
@@ -1023,6 +1036,7 @@ ldpm_status ldpm_set_launch(ldpm_system* s, const ldpm_launch* c)
     s->launch = *c;
     s->launch.xcd_remap = c->xcd_remap ? 1 : 0;
     s->launch.persistent = c->persistent ? 1 : 0;
+    s->launch.stream_facets = c->stream_facets ? 1 : 0;
     return LDPM_OK;
 }
 
@@ -1118,14 +1132,14 @@ ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* 
     std::vector<ldpm_launch> cands;
     for (int i = 0; i < 4; i++)
         for (int j = 0; j < 4; j++)
-            for (int rm = 0; rm < 2; rm++) cands.push_back(ldpm_launch{tbs[i], pts[j], rm, 0});
+            for (int rm = 0; rm < 2; rm++) cands.push_back(ldpm_launch{tbs[i], pts[j], rm, 0, keep.stream_facets});
     if (!s->mblk)
-        for (int i = 0; i < 4; i++) cands.push_back(ldpm_launch{tbs[i], 256, 0, 1});
+        for (int i = 0; i < 4; i++) cands.push_back(ldpm_launch{tbs[i], 256, 0, 1, keep.stream_facets});
     double best_t = 1e300;
     ldpm_launch best_l = keep;
     int32_t nt = 0;
-    for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ci++) {
-        s->launch = cands[ci];
+    auto trial = [&](const ldpm_launch& l) {
+        s->launch = l;
         e = copy_all(false);
         s->step = step0;
         if (e == hipSuccess) e = run_steps(s, 5);  // warm-up: instruction caches, clocks
@@ -1142,6 +1156,13 @@ ldpm_status ldpm_autotune(ldpm_system* s, int32_t steps_per_trial, ldpm_launch* 
             best_t = us;
             best_l = s->launch;
         }
+    };
+    for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ci++) trial(cands[ci]);
+    // the facet streams' cache policy, at the best shape
+    if (e == hipSuccess) {
+        ldpm_launch l = best_l;
+        l.stream_facets = !l.stream_facets;
+        trial(l);
     }
     // restore the state, keep the winner
     if (e == hipSuccess) e = copy_all(false);

@@ -124,9 +124,13 @@ struct ParticleArgs {
 // facet kernel
 // ---------------------------------------------------------------------------
 // Facet records and the traction history are touched once per step, in facet
-// order: they are loaded and stored nontemporally, so that they do not evict
-// what the step reuses from L2 (node records and edge frames, gathered by
-// every tet around them, and the tet-node sums the particle kernel reads).
+// order.  On systems larger than the last-level cache they are loaded and
+// stored nontemporally (NT = 1), so that they do not evict what the step
+// reuses (node records and edge frames, gathered by every tet around them,
+// and the tet-node sums the particle kernel reads); on smaller ones plain
+// accesses (NT = 0) let the whole step stay cache-resident across steps.
+// NT is a template parameter: a run-time choice between the two forms of
+// one load is merged by the compiler into a plain load.
 template <typename T>
 __device__ __forceinline__ T ld_once(const T* p)
 {
@@ -141,26 +145,39 @@ __device__ __forceinline__ void st_once(T v, T* p)
 typedef double quad_d2 __attribute__((ext_vector_type(2)));
 typedef float quad_f4 __attribute__((ext_vector_type(4)));
 
-// the four values of facet f (quad layout), loaded / stored once
-template <typename R>
+template <int NT, typename T>
+__device__ __forceinline__ T ld_facet(const T* p)
+{
+    if constexpr (NT) return ld_once(p);
+    else return *p;
+}
+template <int NT, typename T>
+__device__ __forceinline__ void st_facet(T v, T* p)
+{
+    if constexpr (NT) st_once(v, p);
+    else *p = v;
+}
+
+// the four values of facet f (quad layout)
+template <int NT, typename R>
 __device__ __forceinline__ void ld_quad(const R* base, int64_t F, int64_t f, R& a, R& b, R& c, R& e)
 {
     if constexpr (sizeof(R) == 8) {
-        const quad_d2 x = ld_once((const quad_d2*)base + f), y = ld_once((const quad_d2*)base + F + f);
+        const quad_d2 x = ld_facet<NT>((const quad_d2*)base + f), y = ld_facet<NT>((const quad_d2*)base + F + f);
         a = x.x; b = x.y; c = y.x; e = y.y;
     } else {
-        const quad_f4 x = ld_once((const quad_f4*)base + f);
+        const quad_f4 x = ld_facet<NT>((const quad_f4*)base + f);
         a = x.x; b = x.y; c = x.z; e = x.w;
     }
 }
-template <typename R>
+template <int NT, typename R>
 __device__ __forceinline__ void st_quad(R* base, int64_t F, int64_t f, R a, R b, R c, R e)
 {
     if constexpr (sizeof(R) == 8) {
-        st_once(quad_d2{a, b}, (quad_d2*)base + f);
-        st_once(quad_d2{c, e}, (quad_d2*)base + F + f);
+        st_facet<NT>(quad_d2{a, b}, (quad_d2*)base + f);
+        st_facet<NT>(quad_d2{c, e}, (quad_d2*)base + F + f);
     } else {
-        st_once(quad_f4{a, b, c, e}, (quad_f4*)base + f);
+        st_facet<NT>(quad_f4{a, b, c, e}, (quad_f4*)base + f);
     }
 }
 
@@ -261,7 +278,7 @@ struct SgCount {
 // One tile of TB tetrahedra (block-wide: every thread of a 12 TB block calls
 // it together).  do_prog: this block also evaluates the time programs.
 // cnt (surrogate mode): the lane's running counts.
-template <typename R, int LAW, int TB, int MODE>
+template <typename R, int LAW, int TB, int MODE, int NT = 0>
 __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const NodeArgs& na, const FacetArgs<R>& fa,
                                            const MatDev<R>& mat, const int32_t* __restrict__ pos,
                                            R* __restrict__ contrib, double* __restrict__ wint,
@@ -296,15 +313,15 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     R emx = R(0);
     if (fvalid) {
         const int64_t F = fa.F, E = fa.E;
-        rc = ld_once(&fa.rec[f]);
+        rc = ld_facet<NT>(&fa.rec[f]);
         const int64_t r = rc & 0x0fffffff;
         const R* fr = fa.frame + r * 8;
         n0 = fr[0]; n1 = fr[1]; n2 = fr[2];
         m0 = fr[3]; m1 = fr[4]; m2 = fr[5];
         len = fr[6];
         ilen = fr[7];
-        ld_quad(fa.geo, F, f, cI0, cI1, cI2, A);
-        ld_quad((const R*)fa.hist, F, f, tv[0], tv[1], tv[2], emx);
+        ld_quad<NT>(fa.geo, F, f, cI0, cI1, cI2, A);
+        ld_quad<NT>((const R*)fa.hist, F, f, tv[0], tv[1], tv[2], emx);
     }
     // output position (incidence order) of the tet-node sums of phase D, and
     // the tet's accumulated internal work
@@ -532,7 +549,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
             }
         }
         if (fvalid) {
-            st_quad(fa.hist, F, f, tv[0], tv[1], tv[2], emx);
+            st_quad<NT>(fa.hist, F, f, tv[0], tv[1], tv[2], emx);
             // internal work A l (t_old + t)/2 . de
             wk = (double)(A * len * R(0.5) *
                           ((told[0] + tv[0]) * de[0] + (told[1] + tv[1]) * de[1] + (told[2] + tv[2]) * de[2]));
@@ -594,7 +611,7 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     }
 }
 
-template <typename R, int LAW, int TB, int MODE>
+template <typename R, int LAW, int TB, int MODE, int NT = 0>
 __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa, MatDev<R> mat,
                                                    const int32_t* __restrict__ pos,
                                                    R* __restrict__ contrib, double* __restrict__ wint,
@@ -602,8 +619,8 @@ __global__ __launch_bounds__(12 * TB) void k_facet(NodeArgs na, FacetArgs<R> fa,
                                                    SurrogateArgs sg, CaptureArgs cp)
 {
     if constexpr (MODE == MODE_SURROGATE) mlp_load_frag(sg.params, mlp_smem(), threadIdx.x, 12 * TB);
-    facet_tile<R, LAW, TB, MODE>(xcd_block(blockIdx.x, gridDim.x, remap), blockIdx.x == 0, na, fa, mat, pos,
-                                 contrib, wint, pr, step, dt, sg, cp);
+    facet_tile<R, LAW, TB, MODE, NT>(xcd_block(blockIdx.x, gridDim.x, remap), blockIdx.x == 0, na, fa, mat, pos,
+                                     contrib, wint, pr, step, dt, sg, cp);
 }
 
 // Grid-stride loop over tiles: blocks stay resident and load the surrogate's

@@ -88,7 +88,12 @@ class Info(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("tets_per_block", C.c_int32), ("particle_threads", C.c_int32),
-                ("xcd_remap", C.c_int32), ("persistent", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("persistent", C.c_int32), ("stream_facets", C.c_int32)]
+
+
+def _launch_dict(c):
+    return dict(tets_per_block=c.tets_per_block, particle_threads=c.particle_threads, xcd_remap=c.xcd_remap,
+                persistent=c.persistent, stream_facets=c.stream_facets)
 
 
 class TuneTrial(C.Structure):
@@ -418,15 +423,17 @@ class System:
         _check(lib().ldpm_get_info(self.h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in Info._fields_}
 
-    def set_launch(self, tets_per_block=16, particle_threads=256, xcd_remap=1, persistent=0):
-        c = Launch(tets_per_block, particle_threads, xcd_remap, persistent)
+    def set_launch(self, tets_per_block=16, particle_threads=256, xcd_remap=1, persistent=0, stream_facets=None):
+        """stream_facets None keeps the handle's current setting."""
+        if stream_facets is None:
+            stream_facets = self.get_launch()["stream_facets"]
+        c = Launch(tets_per_block, particle_threads, xcd_remap, persistent, stream_facets)
         _check(lib().ldpm_set_launch(self.h, C.byref(c)))
 
     def get_launch(self):
         c = Launch()
         _check(lib().ldpm_get_launch(self.h, C.byref(c)))
-        return dict(tets_per_block=c.tets_per_block, particle_threads=c.particle_threads,
-                    xcd_remap=c.xcd_remap, persistent=c.persistent)
+        return _launch_dict(c)
 
     def autotune(self, steps_per_trial=100):
         """Time every launch shape on this system, keep the fastest.  Returns
@@ -438,11 +445,8 @@ class System:
         nt = C.c_int32()
         _check(lib().ldpm_autotune(self.h, int(steps_per_trial), C.byref(best), C.byref(us),
                                    arr, cap, C.byref(nt)))
-        as_dict = lambda l: dict(tets_per_block=l.tets_per_block,
-                                 particle_threads=l.particle_threads, xcd_remap=l.xcd_remap,
-                                 persistent=l.persistent)
-        trials = [(as_dict(arr[i].launch), arr[i].us_per_step) for i in range(min(nt.value, cap))]
-        return as_dict(best), us.value, trials
+        trials = [(_launch_dict(arr[i].launch), arr[i].us_per_step) for i in range(min(nt.value, cap))]
+        return _launch_dict(best), us.value, trials
 
     def set_surrogate(self, params, x_mean, x_scale, y_scale, box_lo, box_hi,
                       kappa_t=1.1, kappa_c=0.9, damage_max=0.05, y_dead=(0.0, 0.0, 0.0), y_tau=0.0):

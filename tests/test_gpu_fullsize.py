@@ -115,6 +115,7 @@ def test_cylinder_bench_one_step_and_trajectory_from_a_loaded_state():
     st = _cylinder_loaded_state(s)
     o = _oracle_from(s, st)
     g = gpu(s, init_state=st)
+    assert g.get_launch()["stream_facets"] == 1  # 1.6 GB per launch: facet streams bypass the caches
     o.step(1)
     g.step(1)
     sig_t = s["material"]["sigma_t"]

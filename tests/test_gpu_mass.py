@@ -125,7 +125,7 @@ def test_cell_block_rejects_the_persistent_launch_and_tunes_without_it():
     with pytest.raises(LdpmError, match="persistent"):
         g.set_launch(tets_per_block=16, persistent=1)
     best, us, trials = g.autotune(steps_per_trial=5)
-    assert len(trials) == 32 and best["persistent"] == 0
+    assert len(trials) == 33 and best["persistent"] == 0
 
 
 def test_sphere_variant_against_the_oracle():

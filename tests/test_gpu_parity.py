@@ -164,15 +164,32 @@ def test_determinism_bitwise():
 def test_launch_shape_does_not_change_results():
     s = tension_small()
     ref = None
-    for tb, pt, rm in ((16, 256, 1), (32, 128, 0), (64, 512, 1), (16, 64, 0), (8, 256, 1)):
+    for tb, pt, rm, sf in ((16, 256, 1, 0), (32, 128, 0, 1), (64, 512, 1, 0), (16, 64, 0, 1), (8, 256, 1, 1),
+                           (16, 256, 1, 1)):
         g = gpu(s)
-        g.set_launch(tets_per_block=tb, particle_threads=pt, xcd_remap=rm)
+        g.set_launch(tets_per_block=tb, particle_threads=pt, xcd_remap=rm, stream_facets=sf)
+        assert g.get_launch()["stream_facets"] == sf
         st = g.step(300).read_state()
         if ref is None:
             ref = st
         else:
             for k in ("q", "v", "t", "emax", "w_int"):
-                assert np.array_equal(st[k], ref[k]), (tb, pt, rm, k)
+                assert np.array_equal(st[k], ref[k]), (tb, pt, rm, sf, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_facet_stream_policy_default_and_results(precision):
+    """stream_facets defaults by the facet kernel's bytes per launch (off
+    for the small cube) and either setting gives the same state bitwise."""
+    s = tension_small()
+    g = gpu(s, precision=precision)
+    assert g.get_launch()["stream_facets"] == 0
+    a = g.step(200).read_state()
+    h = gpu(s, precision=precision)
+    h.set_launch(tets_per_block=16, stream_facets=1)
+    b = h.step(200).read_state()
+    for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
+        assert np.array_equal(a[k], b[k]), k
 
 
 def test_resume_is_bitwise():
@@ -342,7 +359,7 @@ def test_autotune_keeps_the_trajectory():
     ref = gpu(s).step(300).read_state()
     g = gpu(s).step(100)
     best, us, trials = g.autotune(steps_per_trial=20)
-    assert len(trials) == 36 and us > 0
+    assert len(trials) == 37 and us > 0
     assert best in [t[0] for t in trials]
     st = g.step(200).read_state()
     for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
