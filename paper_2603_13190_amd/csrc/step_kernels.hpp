@@ -572,31 +572,52 @@ __device__ __forceinline__ void facet_tile(int64_t blk, bool do_prog, const Node
     }
     __syncthreads();
 
-    // ---- D: per tet node, sum its 6 facets in ascending local order and
+    // ---- D: per tet node, sum its facets in ascending local order and
     //      write the sum at the node's incidence position ----
     if (tid < NS) {
         const int tl = tid >> 2, a = tid & 3;
         const int64_t tt = tet0 + tl;
         if (tt < T) {
             R acc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-            // the tet's 12 codes in three words; each facet adds sg * value
-            // with sg = +1 (node on the I side), -1 (J side) or 0 (not on the
-            // facet): fma(+-1, x, acc) rounds like acc +- x
+            // the tet's 12 codes in three words -> the facets on this node
+            // (bit j) and those with the node on their J side
             const uint32_t* cw = reinterpret_cast<const uint32_t*>(s_code) + tl * 3;
             const uint32_t w0 = cw[0], w1 = cw[1], w2 = cw[2];
+            uint32_t on = 0, onJ = 0;
 #pragma unroll
             for (int j = 0; j < 12; j++) {
-                const int fl = tl * 12 + j;
                 const int cd = (int)(((j < 4 ? w0 : (j < 8 ? w1 : w2)) >> (8 * (j & 3))) & 0xff);
-                const bool onI = (cd & 3) == a;
-                const bool onJ = ((cd >> 2) & 3) == a;
-                const R sg = onI ? R(1) : (onJ ? R(-1) : R(0));
-                const R* mrow = onI ? &s_MI[0][fl] : &s_MJ[0][fl];
+                const bool isI = (cd & 3) == a;
+                const bool isJ = ((cd >> 2) & 3) == a;
+                on |= (uint32_t)(isI || isJ) << j;
+                onJ |= (uint32_t)isJ << j;
+            }
+            // facet j adds +-(F, M): fma(+-1, x, acc) rounds like acc +- x
+            auto add = [&](int j) {
+                const int fl = tl * 12 + j;
+                const bool jside = (onJ >> j) & 1u;
+                const R sg = jside ? R(-1) : R(1);
+                const R* mrow = jside ? &s_MJ[0][fl] : &s_MI[0][fl];
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     acc[c] = d_fma(sg, s_F[c][fl], acc[c]);
                     acc[3 + c] = d_fma(sg, mrow[c * NF], acc[3 + c]);
                 }
+            };
+            // ascending j over the node's facets: six in every LDPM tet (two
+            // per edge, three edges per node), any number otherwise
+            if (__builtin_popcount(on) == 6) {
+                int idx[6];
+                uint32_t m = on;
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    idx[k] = __builtin_ctz(m);
+                    m &= m - 1;
+                }
+#pragma unroll
+                for (int k = 0; k < 6; k++) add(idx[k]);
+            } else {
+                for (uint32_t m = on; m; m &= m - 1) add(__builtin_ctz(m));
             }
             R* out = contrib + (int64_t)opos * 6;
 #pragma unroll
