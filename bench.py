@@ -157,6 +157,12 @@ def batched_case(args, tune):
                      "facet_kernel_avg_us": favg * 1e3,
                      "facet_kernel_GBs": info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9,
                      "facet_kernel_frac_hbm": info["facet_kernel_bytes"] / (favg * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        if prec == "fp64":
+            # the field kernels on a large system (the crack-opening field of
+            # the batch's state and its comparison with itself)
+            w = g.crack_opening()
+            rec[prec]["field_kernels"] = kernel_rates(g, w, w[3].clone())
+            del w
         g.close()
         log(f"batched {prec}: {v:.4e} facet-upd/s, facet kernel {favg * 1e3:.1f} us "
             f"({rec[prec]['facet_kernel_GBs']:.0f} GB/s)")
@@ -189,11 +195,12 @@ def field_stats(x, ref, cap=None):
 
 def crack_kernel_bytes(info):
     """Compulsory HBM bytes of one crack-opening launch: per facet the record
-    id (4 B), c^I and t (6 R) and the written w (4 doubles); per edge frame
-    8 R; per tetrahedron the two node ids the facets use (16 B); per
-    particle q and v (12 doubles)."""
+    id (4 B), the geometry and history quads that hold c^I and t (8 R: area
+    and e_max share their 16-byte chunks) and the written w (4 doubles); per
+    edge frame 8 R; per tetrahedron the two node ids the facets use (16 B);
+    per particle q and v (12 doubles)."""
     rb = 4.0 if info["precision"] == 1 else 8.0
-    return (info["n_facets"] * (4.0 + 6.0 * rb + 32.0) + info["n_edges"] * 8.0 * rb + info["n_tets"] * 16.0
+    return (info["n_facets"] * (4.0 + 8.0 * rb + 32.0) + info["n_edges"] * 8.0 * rb + info["n_tets"] * 16.0
             + info["n_particles"] * 96.0)
 
 

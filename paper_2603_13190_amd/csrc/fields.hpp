@@ -93,12 +93,15 @@ __global__ __launch_bounds__(12 * TB) void k_crack(NodeArgs na, FacetArgs<R> fa,
     if (valid) {
         rc = fa.rec[f];
         const R* fr = fa.frame + (int64_t)(rc & 0x0fffffff) * 8;
+        R g[4], h[4];
+        ld_quad<0>(fa.geo, F, f, g[0], g[1], g[2], g[3]);
+        ld_quad<0>((const R*)fa.hist, F, f, h[0], h[1], h[2], h[3]);
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             n[c] = (double)fr[c];
             m[c] = (double)fr[3 + c];
-            cI[c] = (double)fa.geo[quad_index<R>(F, f, c)];
-            t[c] = (double)fa.hist[quad_index<R>(F, f, c)];
+            cI[c] = (double)g[c];
+            t[c] = (double)h[c];
         }
         len = (double)fr[6];
     }
