@@ -361,6 +361,9 @@ def test_autotune_keeps_the_trajectory():
     best, us, trials = g.autotune(steps_per_trial=20)
     assert len(trials) == 37 and us > 0
     assert best in [t[0] for t in trials]
+    # 36 shapes at the handle's facet-stream policy, then the best one with the other
+    assert {t[0]["stream_facets"] for t in trials[:36]} == {0}
+    assert trials[36][0] == dict(min(trials[:36], key=lambda t: t[1])[0], stream_facets=1)
     st = g.step(200).read_state()
     for k in ("q", "v", "t", "emax", "fext", "w_int", "w_ext", "w_kin"):
         assert np.array_equal(st[k], ref[k]), k
